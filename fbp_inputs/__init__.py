@@ -16,6 +16,7 @@ from .phantom import (  # noqa: F401
     linogram,
     parallel_sinogram,
     poisson_noisy,
+    volume_linogram,
     random_int_array,
     support_mask,
 )

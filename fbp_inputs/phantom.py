@@ -257,3 +257,17 @@ def support_mask(n: int, *, disc: float = 0.34, device=None) -> torch.Tensor:
     """Boolean [N, N] mask of pixels whose centres lie in the disc of radius disc * N."""
     c = torch.arange(n, device=device, dtype=F64) + 0.5 - 0.5 * n
     return (c[:, None] ** 2 + c[None, :] ** 2) <= (disc * n) ** 2
+
+
+def volume_linogram(n: int, depth: int, *, count: int = 30, seed: int = 3, device=None,
+                    dtype=torch.float32, chunk: int = 8):
+    """Linograms of every z-slice of a seeded ellipsoid volume: [depth, 4, N, N].
+
+    ``count`` ellipsoids (one axis along z, see :func:`random_ellipsoids`) are cut at the slice
+    centres and each cross-section's exact line integrals are evaluated on ``device``.
+    Returns (linogram, slice ellipse sets).
+    """
+    e3 = random_ellipsoids(n, depth, count, seed)
+    sl = ellipsoid_slices(e3, depth)
+    lino = linogram(sl, n, device=device, dtype=dtype, chunk=chunk)
+    return lino, sl

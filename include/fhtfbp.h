@@ -1,0 +1,155 @@
+/*
+ * fhtfbp.h -- C ABI of the accelerated filtered back projection library (HIP, gfx950).
+ *
+ * Method: Dolmatova, Chukalina, Nikolaev, "Accelerated FBP for computed tomography image
+ * reconstruction" (ICIP 2020).  A CT slice of N x N pixels (N = 2^n) is rebuilt from its
+ * linogram: four N x N images of line integrals, one per line class of the (s, t)
+ * parameterisation (Sec. 4.1).  Each detector row is ramp-filtered by a causal plus an
+ * anticausal recursive filter (Sec. 3, eq 9-13); the filtered classes are back-projected by
+ * the transposed dyadic Fast Hough Transform (Sec. 4.4-4.5, eq 19-21) and summed (eq 22).
+ *
+ * Data layout (all float32, row-major, caller-owned device memory):
+ *   linogram  [batch][4][N][N]   index [b][q][t][s]: class q, slope index t, cyclic shift s
+ *   image     [batch][N][N]      index [b][y][x]: pixel row y, column x
+ * Class q: 0 = mostly vertical lines with positive shift (x = s + m_t y), 1 = mostly vertical
+ * with negative shift (mirror of 0 in x), 2 = mostly horizontal with positive shift (class 0
+ * of the transposed image, eq 16), 3 = mostly horizontal with negative shift.  Slope
+ * m_t = t / (N - 1).  Linogram values are physical line integrals.
+ *
+ * Conventions: every call returns 0 or a negative FBP_E* code; argument errors are detected
+ * before anything is launched; nothing throws across the ABI.  Calls enqueue work on the
+ * plan's HIP stream and return without synchronising.  Pointers must be device pointers
+ * (or host-visible device memory) aligned to 16 bytes.  A plan is not thread-safe: do not
+ * issue calls on one plan from several host threads at once.
+ */
+#ifndef FHTFBP_H
+#define FHTFBP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ---------------------------------------------------------------------- */
+#define FBP_OK          0
+#define FBP_EINVAL     -1   /* bad argument: null pointer, N not a power of two, order ... */
+#define FBP_EUNSTABLE  -2   /* recursive filter has a pole with |p| >= 1 (or a NaN/Inf)    */
+#define FBP_ENOMEM     -3   /* device allocation failed                                    */
+#define FBP_EDEVICE    -4   /* a HIP call or kernel launch failed                          */
+#define FBP_ERANGE     -5   /* batch above the plan's max_batch, or a size out of range    */
+
+/* ---- plan flags ----------------------------------------------------------------------- */
+#define FBP_NO_ROW_SCALE  1u  /* skip the per-row factor c_t = k_t * w_t after the filter  */
+#define FBP_INPUT_IS_FHT  2u  /* rows are sums over image rows (eq 15 normalisation): apply
+                                 one more k_t, i.e. c_t = k_t^2 * w_t                      */
+#define FBP_ZERO_WINDOW   4u  /* filter every row over shifts 0..N-1 instead of the window
+                                 centred on the row's central intercept                   */
+
+typedef struct fbp_plan_s* fbp_plan_t;
+
+typedef struct {
+  int32_t n;          /* N: power of two, 4 <= N <= 4096 (the dyadic FHT needs 2^k, Sec 4.4) */
+  int32_t max_batch;  /* largest batch any call on this plan will pass (>= 1)                */
+  int32_t order;      /* K = M = Q of eq 9 (the paper's experiments use Q = M), 1..8          */
+  int32_t groups;     /* coefficient sets: the 4N rows in (q, t) order are split into
+                         `groups` equal consecutive ranges (angle groups); 1 = one set; must
+                         divide 4N and be <= 64                                               */
+  const double* b;    /* host [groups][order]: feed-forward b_0..b_{K-1} (eq 9); the causal
+                         and the anticausal pass share them (Sec. 3)                          */
+  const double* a;    /* host [groups][order]: feedback a_1..a_K (eq 9)                        */
+  uint32_t flags;     /* FBP_* flags above                                                    */
+  void* stream;       /* hipStream_t used by every call (NULL = default stream)               */
+} fbp_plan_desc;
+
+/* Create a plan: validates the description, checks filter stability (every root of
+ * 1 + a_1 z^-1 + ... + a_K z^-K inside the unit circle), builds the per-row tables (window
+ * start, row scale c_t), the chunk transition matrices of the recursive filter, and
+ * allocates the inter-pass scratch (2 x max_batch x 16 N^2 bytes at most).  Synchronous.
+ * On error *out is set to NULL and nothing is allocated. */
+int fbp_plan(const fbp_plan_desc* desc, fbp_plan_t* out);
+
+/* Release the plan and its device memory (synchronises its stream first).  NULL is a no-op. */
+int fbp_plan_destroy(fbp_plan_t plan);
+
+/* Switch the stream later calls enqueue on. */
+int fbp_plan_set_stream(fbp_plan_t plan, void* stream);
+
+/* Replace the recursive-filter coefficients (host arrays shaped as in the description).
+ * Synchronises the plan's stream, checks stability, uploads.  Used by the learned filter. */
+int fbp_plan_set_coefficients(fbp_plan_t plan, const double* b, const double* a);
+
+/* Row filter alone (Sec. 3, eq 12-13): every linogram row (b, q, t) is read over its window
+ * of N cyclic shifts, run through the causal and the anticausal recursion with zero state
+ * outside the window, summed, scaled by c_t and written to the same shifts of `lino_out`.
+ * In-place (lino_out == lino_in) is allowed.  batch == 0 is a no-op. */
+int fbp_filter(fbp_plan_t plan, const float* lino_in, float* lino_out, int32_t batch);
+
+/* Back projection alone (Sec. 4.5, eq 19-22): img = sum over the four classes of the
+ * transposed dyadic FHT of the class, mapped back to the image frame.  No filtering.
+ * `lino` and `img` must not overlap. */
+int fht_backproject(fbp_plan_t plan, const float* lino, float* img, int32_t batch);
+
+/* Forward projection by the dyadic FHT (eq 16-17): lino[b][q][t][s] = sum over image rows of
+ * the class-q frame along the dyadic pattern (t, s) (row-sum normalisation, no k_t).  Exact
+ * adjoint of fht_backproject.  `img` and `lino` must not overlap. */
+int fht_forward(fbp_plan_t plan, const float* img, float* lino, int32_t batch);
+
+/* The method end to end: fbp_filter then fht_backproject, with the filter fused into the
+ * first back-projection pass (the linogram is read once).  `lino` is not modified. */
+int fbp_reconstruct(fbp_plan_t plan, const float* lino, float* img, int32_t batch);
+
+/* Host-side fit of the recursive ramp pair (Sec. 3): minimise the squared error between the
+ * impulse response of eq 9 and the causal half h+ of eq 10 over n = 0..length-1 by the
+ * Nelder-Mead simplex method (a parameterised through reflection coefficients, so the fit is
+ * always stable; b by linear least squares for each a).  flags bit 0: constrain
+ * sum(b) = 0 (zero response at zero frequency, as the ramp has).  Writes b[order],
+ * a[order] and the relative L2 error of the fit.  Deterministic.  No GPU needed. */
+int fbp_fit_ramp_iir(int32_t order, int32_t length, uint32_t flags, double* b, double* a,
+                     double* rel_err);
+
+/* Direct FBP comparator on a uniform parallel-beam sinogram (Sec. 2, eq 3-5 with the exact
+ * ramp of eq 7-8): sino [batch][n_angles][n_det], angle i = i pi / n_angles (unit normal
+ * (cos, sin)), detector j at signed distance j - n_det/2 + 1/2 from the image centre.  Each
+ * row is filtered by the full-length FIR and weighted pi / n_angles into `work`
+ * ([batch][n_angles][n_det] floats, caller-owned), then back-projected with linear
+ * interpolation into img [batch][n][n].  Theta(n_angles n^2) per slice. */
+int fbp_direct_parallel(const float* sino, float* work, float* img, int32_t batch, int32_t n,
+                        int32_t n_angles, int32_t n_det, void* stream);
+
+/* The two halves of fbp_direct_parallel, for timing them apart. */
+int fbp_direct_filter(const float* sino, float* work, int32_t batch, int32_t n_angles,
+                      int32_t n_det, void* stream);
+int fbp_direct_backproject(const float* work, float* img, int32_t batch, int32_t n,
+                           int32_t n_angles, int32_t n_det, void* stream);
+
+/* ---- kernel timing -------------------------------------------------------------------- */
+/* Kernel kinds reported by fbp_plan_profile_read. */
+#define FBP_KERNEL_FIRST   0  /* first back-projection pass (with the filter in reconstruct) */
+#define FBP_KERNEL_MIDDLE  1  /* middle back-projection passes (N >= 2048)                   */
+#define FBP_KERNEL_LAST_V  2  /* last pass, classes 0 + 1 into image rows                    */
+#define FBP_KERNEL_LAST_H  3  /* last pass, classes 2 + 3 added into image columns          */
+#define FBP_KERNEL_FORWARD 4  /* forward-transform passes                                    */
+#define FBP_KERNEL_FILTER  5  /* filter alone                                                */
+#define FBP_KERNEL_KINDS   6
+
+/* enable != 0: clear and start recording a HIP event pair around every kernel the plan launches
+ * (on the plan's stream, so the events time exactly that launch); enable == 0: stop.  Costs
+ * two event records per launch and no synchronisation. */
+int fbp_plan_profile(fbp_plan_t plan, int32_t enable);
+
+/* Synchronise the recorded events, write per-kind total milliseconds and launch counts
+ * (arrays of FBP_KERNEL_KINDS entries) and clear the record. */
+int fbp_plan_profile_read(fbp_plan_t plan, double* total_ms, int32_t* launches);
+
+/* Human-readable text of an error code (static storage). */
+const char* fbp_strerror(int code);
+
+/* Number of HBM passes and fused levels per pass the plan uses (for reports): writes up to
+ * `cap` entries into levels[] and returns the pass count, or a negative error. */
+int fbp_plan_passes(fbp_plan_t plan, int32_t* levels, int32_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FHTFBP_H */

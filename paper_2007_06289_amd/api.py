@@ -1,0 +1,319 @@
+"""Python binding of libfhtfbp (the C ABI declared in include/fhtfbp.h).
+
+Argument marshalling only: tensors are checked for device, dtype, contiguity and shape, and
+their device pointers are handed to the library together with torch's current HIP stream.
+Every step of the computation runs in the library's HIP kernels; there is no fallback, and a
+missing library raises an error.
+
+Layouts (float32, contiguous, on the GPU):
+    linogram [B, 4, N, N]  (class q, slope index t, cyclic shift s)
+    image    [B, N, N]
+    sinogram [B, P, Nd]    (uniform parallel beam, for the direct-FBP comparator)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfhtfbp.so")
+
+FBP_OK = 0
+FBP_EINVAL = -1
+FBP_EUNSTABLE = -2
+FBP_ENOMEM = -3
+FBP_EDEVICE = -4
+FBP_ERANGE = -5
+
+FBP_NO_ROW_SCALE = 1
+FBP_INPUT_IS_FHT = 2
+FBP_ZERO_WINDOW = 4
+
+FIT_DC_ZERO = 1
+
+_lib = None
+
+
+class FbpError(RuntimeError):
+    """A libfhtfbp call returned an error code."""
+
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+
+
+class _PlanDesc(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32),
+        ("max_batch", ctypes.c_int32),
+        ("order", ctypes.c_int32),
+        ("groups", ctypes.c_int32),
+        ("b", ctypes.POINTER(ctypes.c_double)),
+        ("a", ctypes.POINTER(ctypes.c_double)),
+        ("flags", ctypes.c_uint32),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+def load_library():
+    """Load libfhtfbp.so (built in-tree by ``paper_2007_06289_amd._build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2007_06289_amd._build` (or __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32
+    dp = ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "fbp_plan": ([ctypes.POINTER(_PlanDesc), ctypes.POINTER(vp)], ctypes.c_int),
+        "fbp_plan_destroy": ([vp], ctypes.c_int),
+        "fbp_plan_set_stream": ([vp, vp], ctypes.c_int),
+        "fbp_plan_set_coefficients": ([vp, dp, dp], ctypes.c_int),
+        "fbp_plan_passes": ([vp, ctypes.POINTER(i32), i32], ctypes.c_int),
+        "fbp_filter": ([vp, vp, vp, i32], ctypes.c_int),
+        "fht_backproject": ([vp, vp, vp, i32], ctypes.c_int),
+        "fht_forward": ([vp, vp, vp, i32], ctypes.c_int),
+        "fbp_reconstruct": ([vp, vp, vp, i32], ctypes.c_int),
+        "fbp_fit_ramp_iir": ([i32, i32, u32, dp, dp, dp], ctypes.c_int),
+        "fbp_direct_parallel": ([vp, vp, vp, i32, i32, i32, i32, vp], ctypes.c_int),
+        "fbp_direct_filter": ([vp, vp, i32, i32, i32, vp], ctypes.c_int),
+        "fbp_direct_backproject": ([vp, vp, i32, i32, i32, i32, vp], ctypes.c_int),
+        "fbp_strerror": ([ctypes.c_int], ctypes.c_char_p),
+        "fbp_plan_profile": ([vp, i32], ctypes.c_int),
+        "fbp_plan_profile_read": ([vp, dp, ctypes.POINTER(i32)], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def strerror(code: int) -> str:
+    return load_library().fbp_strerror(int(code)).decode()
+
+
+def _check(rc: int, what: str):
+    if rc != FBP_OK:
+        raise FbpError(rc, what)
+
+
+def _stream_ptr():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_ptr(t: torch.Tensor, name: str, shape=None) -> ctypes.c_void_p:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on the GPU (got {t.device})")
+    if t.dtype != torch.float32:
+        raise ValueError(f"{name} must be float32 (got {t.dtype})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _coef_arrays(b, a, order=None):
+    b = np.ascontiguousarray(np.asarray(b, dtype=np.float64))
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if b.ndim == 1:
+        b = b[None]
+    if a.ndim == 1:
+        a = a[None]
+    if b.shape != a.shape:
+        raise ValueError(f"b {b.shape} and a {a.shape} must have the same [groups, order] shape")
+    if order is not None and b.shape[1] != order:
+        raise ValueError(f"coefficients have order {b.shape[1]}, plan has {order}")
+    return b, a
+
+
+class Plan:
+    """An fbp_plan handle (owns the library's per-size tables and inter-pass scratch)."""
+
+    def __init__(self, n: int, max_batch: int, b, a, flags: int = 0):
+        lib = load_library()
+        b, a = _coef_arrays(b, a)
+        self.n = int(n)
+        self.max_batch = int(max_batch)
+        self.groups, self.order = b.shape
+        self.flags = int(flags)
+        self._b, self._a = b, a
+        desc = _PlanDesc(self.n, self.max_batch, self.order, self.groups,
+                         b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                         a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                         self.flags, _stream_ptr() if torch.cuda.is_available() else None)
+        h = ctypes.c_void_p()
+        _check(lib.fbp_plan(ctypes.byref(desc), ctypes.byref(h)), "fbp_plan")
+        self._h = h
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("plan is closed")
+        return self._h
+
+    def bind_stream(self):
+        _check(load_library().fbp_plan_set_stream(self.handle, _stream_ptr()),
+               "fbp_plan_set_stream")
+
+    def passes(self) -> list[int]:
+        buf = (ctypes.c_int32 * 16)()
+        p = load_library().fbp_plan_passes(self.handle, buf, 16)
+        if p < 0:
+            raise FbpError(p, "fbp_plan_passes")
+        return [int(buf[i]) for i in range(p)]
+
+    KERNEL_KINDS = ("first", "middle", "last_v", "last_h", "forward", "filter")
+
+    def profile(self, enable: bool = True):
+        """Start (clearing) or stop recording HIP events around every launch of this plan."""
+        _check(load_library().fbp_plan_profile(self.handle, 1 if enable else 0),
+               "fbp_plan_profile")
+
+    def profile_read(self) -> dict:
+        """{kind: (total_ms, launches)} for the recorded launches (synchronises them)."""
+        ms = (ctypes.c_double * 6)()
+        n = (ctypes.c_int32 * 6)()
+        _check(load_library().fbp_plan_profile_read(self.handle, ms, n), "fbp_plan_profile_read")
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(self.KERNEL_KINDS) if n[i]}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            load_library().fbp_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def fbp_plan(n: int, max_batch: int, b, a, flags: int = 0) -> Plan:
+    """Create a plan (see ``fbp_plan`` in include/fhtfbp.h).  ``b``/``a``: [order] or
+    [groups, order] float64 arrays (b_0..b_{K-1}, a_1..a_K)."""
+    return Plan(n, max_batch, b, a, flags)
+
+
+def fbp_plan_set_coefficients(plan: Plan, b, a):
+    b, a = _coef_arrays(b, a, plan.order)
+    if b.shape[0] != plan.groups:
+        raise ValueError(f"expected {plan.groups} coefficient groups, got {b.shape[0]}")
+    _check(load_library().fbp_plan_set_coefficients(
+        plan.handle, b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+        a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "fbp_plan_set_coefficients")
+    plan._b, plan._a = b, a
+
+
+def _batch_of(t: torch.Tensor, tail_dims: int, name: str) -> int:
+    if t.dim() != tail_dims + 1:
+        raise ValueError(f"{name} must have {tail_dims + 1} dimensions, got {tuple(t.shape)}")
+    return int(t.shape[0])
+
+
+def fbp_filter(plan: Plan, lino_in: torch.Tensor, lino_out: torch.Tensor | None = None):
+    """Recursive ramp-pair filter of every linogram row; ``lino_out`` may be ``lino_in``."""
+    B = _batch_of(lino_in, 3, "lino_in")
+    shape = (B, 4, plan.n, plan.n)
+    if lino_out is None:
+        lino_out = torch.empty(shape, device=lino_in.device, dtype=torch.float32)
+    pin, pout = _dev_ptr(lino_in, "lino_in", shape), _dev_ptr(lino_out, "lino_out", shape)
+    plan.bind_stream()
+    _check(load_library().fbp_filter(plan.handle, pin, pout, B), "fbp_filter")
+    return lino_out
+
+
+def fht_backproject(plan: Plan, lino: torch.Tensor, img: torch.Tensor | None = None):
+    """Transposed-FHT back projection of the four classes, summed: [B,4,N,N] -> [B,N,N]."""
+    B = _batch_of(lino, 3, "lino")
+    if img is None:
+        img = torch.empty((B, plan.n, plan.n), device=lino.device, dtype=torch.float32)
+    pl = _dev_ptr(lino, "lino", (B, 4, plan.n, plan.n))
+    pi = _dev_ptr(img, "img", (B, plan.n, plan.n))
+    plan.bind_stream()
+    _check(load_library().fht_backproject(plan.handle, pl, pi, B), "fht_backproject")
+    return img
+
+
+def fht_forward(plan: Plan, img: torch.Tensor, lino: torch.Tensor | None = None):
+    """Dyadic FHT forward projection on the four classes: [B,N,N] -> [B,4,N,N]."""
+    B = _batch_of(img, 2, "img")
+    if lino is None:
+        lino = torch.empty((B, 4, plan.n, plan.n), device=img.device, dtype=torch.float32)
+    pi = _dev_ptr(img, "img", (B, plan.n, plan.n))
+    pl = _dev_ptr(lino, "lino", (B, 4, plan.n, plan.n))
+    plan.bind_stream()
+    _check(load_library().fht_forward(plan.handle, pi, pl, B), "fht_forward")
+    return lino
+
+
+def fbp_reconstruct(plan: Plan, lino: torch.Tensor, img: torch.Tensor | None = None):
+    """Filter plus back projection (the method end to end): [B,4,N,N] -> [B,N,N]."""
+    B = _batch_of(lino, 3, "lino")
+    if img is None:
+        img = torch.empty((B, plan.n, plan.n), device=lino.device, dtype=torch.float32)
+    pl = _dev_ptr(lino, "lino", (B, 4, plan.n, plan.n))
+    pi = _dev_ptr(img, "img", (B, plan.n, plan.n))
+    plan.bind_stream()
+    _check(load_library().fbp_reconstruct(plan.handle, pl, pi, B), "fbp_reconstruct")
+    return img
+
+
+def fbp_fit_ramp_iir(order: int, length: int, dc_zero: bool = True):
+    """Fit the recursive ramp pair on the host; returns (b, a, relative L2 error)."""
+    b = np.zeros(order, dtype=np.float64)
+    a = np.zeros(order, dtype=np.float64)
+    err = ctypes.c_double()
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(load_library().fbp_fit_ramp_iir(int(order), int(length), FIT_DC_ZERO if dc_zero else 0,
+                                           b.ctypes.data_as(dp), a.ctypes.data_as(dp),
+                                           ctypes.byref(err)), "fbp_fit_ramp_iir")
+    return b, a, float(err.value)
+
+
+def fbp_direct_parallel(sino: torch.Tensor, n: int, img: torch.Tensor | None = None,
+                        work: torch.Tensor | None = None):
+    """Direct FBP comparator on a uniform parallel-beam sinogram [B, P, Nd] -> [B, n, n]."""
+    B, P, Nd = _batch_of(sino, 2, "sino"), sino.shape[1], sino.shape[2]
+    if img is None:
+        img = torch.empty((B, n, n), device=sino.device, dtype=torch.float32)
+    if work is None:
+        work = torch.empty((B, P, Nd), device=sino.device, dtype=torch.float32)
+    ps = _dev_ptr(sino, "sino")
+    pw = _dev_ptr(work, "work", (B, P, Nd))
+    pi = _dev_ptr(img, "img", (B, n, n))
+    _check(load_library().fbp_direct_parallel(ps, pw, pi, B, int(n), int(P), int(Nd),
+                                              _stream_ptr()), "fbp_direct_parallel")
+    return img
+
+
+def fbp_direct_filter(sino: torch.Tensor, work: torch.Tensor):
+    B, P, Nd = _batch_of(sino, 2, "sino"), sino.shape[1], sino.shape[2]
+    _check(load_library().fbp_direct_filter(_dev_ptr(sino, "sino"),
+                                            _dev_ptr(work, "work", (B, P, Nd)), B, int(P),
+                                            int(Nd), _stream_ptr()), "fbp_direct_filter")
+    return work
+
+
+def fbp_direct_backproject(work: torch.Tensor, n: int, img: torch.Tensor):
+    B, P, Nd = _batch_of(work, 2, "work"), work.shape[1], work.shape[2]
+    _check(load_library().fbp_direct_backproject(_dev_ptr(work, "work"),
+                                                 _dev_ptr(img, "img", (B, n, n)), B, int(n),
+                                                 int(P), int(Nd), _stream_ptr()),
+           "fbp_direct_backproject")
+    return img

@@ -1,0 +1,7 @@
+// Instantiates the FHT pass kernels for filter chunks of 16 samples (one translation unit per
+// chunk length, so the library builds in parallel).
+#include "fht_pass_impl.h"
+
+namespace fhtfbp {
+template hipError_t launch_pass_l<16>(const PassArgs& a, int batch, hipStream_t stream);
+}  // namespace fhtfbp

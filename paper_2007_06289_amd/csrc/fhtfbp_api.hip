@@ -1,0 +1,516 @@
+// Host side of libfhtfbp: plans, argument checks, pass scheduling and the C ABI entry points.
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "../../include/fhtfbp.h"
+#include "fhtfbp_internal.h"
+
+using namespace fhtfbp;
+
+struct fbp_plan_s {
+  int n = 0, log2n = 0, max_batch = 0, order = 0, groups = 1;
+  uint32_t flags = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int log2l = 0, log2c = 0;   // chunk length and chunks per row of the filter
+  int rs = 0;                 // LDS row stride
+  std::vector<int> levels;    // levels per pass, first pass first
+  std::vector<double> b, a;   // host copies [groups][order]
+  int coef_stride = 0;
+  float* d_coef = nullptr;
+  float* d_scale = nullptr;
+  int* d_sigma = nullptr;
+  float* d_scratch[2] = {nullptr, nullptr};
+  size_t scratch_floats = 0;
+  // kernel timing: event pairs recorded around launches while profiling is on
+  bool profiling = false;
+  struct Rec {
+    hipEvent_t start, stop;
+    int kind;
+  };
+  std::vector<Rec> recs;
+};
+
+namespace {
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2(int v) {
+  int r = 0;
+  while ((1 << r) < v) ++r;
+  return r;
+}
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+// Schur-Cohn step-down test: every root of 1 + a_1 z^-1 + ... + a_K z^-K inside |z| < 1.
+bool stable(const double* a, int K) {
+  std::vector<double> c(K + 1);
+  c[0] = 1.0;
+  for (int k = 0; k < K; ++k) {
+    if (!isfinite(a[k])) return false;
+    c[k + 1] = a[k];
+  }
+  for (int m = K; m >= 1; --m) {
+    const double km = c[m];
+    if (!(fabs(km) < 1.0)) return false;
+    std::vector<double> d(m);
+    const double den = 1.0 - km * km;
+    for (int i = 0; i < m; ++i) d[i] = (c[i] - km * c[m - i]) / den;
+    for (int i = 0; i < m; ++i) c[i] = d[i];
+  }
+  return true;
+}
+
+// Phi_j = C^(L 2^j) for the companion matrix C of the recursion (state (y[i-1], ..., y[i-K])).
+void transition_powers(const double* a, int K, int L, double* out /* [kScanLevels][K][K] */) {
+  std::vector<double> C(K * K, 0.0), P(K * K, 0.0), tmp(K * K);
+  for (int m = 0; m < K; ++m) C[m] = -a[m];
+  for (int i = 1; i < K; ++i) C[i * K + i - 1] = 1.0;
+  auto mul = [&](const std::vector<double>& X, const std::vector<double>& Y,
+                 std::vector<double>& Z) {
+    for (int i = 0; i < K; ++i)
+      for (int j = 0; j < K; ++j) {
+        double s = 0;
+        for (int m = 0; m < K; ++m) s += X[i * K + m] * Y[m * K + j];
+        Z[i * K + j] = s;
+      }
+  };
+  for (int i = 0; i < K; ++i) P[i * K + i] = 1.0;   // P = C^L
+  for (int s = 0; s < L; ++s) {
+    mul(P, C, tmp);
+    P.swap(tmp);
+  }
+  for (int j = 0; j < kScanLevels; ++j) {
+    for (int i = 0; i < K * K; ++i) out[j * K * K + i] = P[i];
+    mul(P, P, tmp);
+    P.swap(tmp);
+  }
+}
+
+// Levels per pass: as few passes as LDS allows, balanced, extra levels to the later passes.
+std::vector<int> split_levels(int n, int fmax) {
+  const int P = (n + fmax - 1) / fmax;
+  std::vector<int> v(P, n / P);
+  for (int i = 0; i < n % P; ++i) v[P - 1 - i] += 1;
+  return v;
+}
+
+int upload_coefficients(fbp_plan_s* p) {
+  const int K0 = p->order, G = p->groups;
+  const int K = kernel_order(K0);   // taps K0..K-1 are zero
+  const int L = 1 << p->log2l;
+  std::vector<float> host((size_t)G * p->coef_stride, 0.f);
+  std::vector<double> phi(kScanLevels * K * K);
+  for (int g = 0; g < G; ++g) {
+    std::vector<double> bg(K, 0.0), ag(K, 0.0);
+    for (int k = 0; k < K0; ++k) {
+      bg[k] = p->b[(size_t)g * K0 + k];
+      ag[k] = p->a[(size_t)g * K0 + k];
+    }
+    if (!stable(ag.data(), K0)) return FBP_EUNSTABLE;
+    for (int k = 0; k < K; ++k) {
+      if (!isfinite(bg[k])) return FBP_EUNSTABLE;
+      host[(size_t)g * p->coef_stride + k] = (float)bg[k];
+      host[(size_t)g * p->coef_stride + K + k] = (float)ag[k];
+    }
+    transition_powers(ag.data(), K, L, phi.data());
+    for (int i = 0; i < kScanLevels * K * K; ++i)
+      host[(size_t)g * p->coef_stride + 2 * K + i] = (float)phi[i];
+  }
+  if (hipStreamSynchronize(p->stream) != hipSuccess) return FBP_EDEVICE;
+  if (hipMemcpy(p->d_coef, host.data(), host.size() * sizeof(float), hipMemcpyHostToDevice) !=
+      hipSuccess)
+    return FBP_EDEVICE;
+  return FBP_OK;
+}
+
+void clear_recs(fbp_plan_s* p) {
+  for (auto& r : p->recs) {
+    hipEventDestroy(r.start);
+    hipEventDestroy(r.stop);
+  }
+  p->recs.clear();
+}
+
+// Launch one pass, bracketed by timing events when the plan is profiling.
+hipError_t timed_pass(fbp_plan_s* p, const PassArgs& A, int batch, int kind) {
+  if (!p->profiling) return launch_pass(A, batch, p->stream);
+  fbp_plan_s::Rec r;
+  r.kind = kind;
+  if (hipEventCreate(&r.start) != hipSuccess) return hipErrorOutOfMemory;
+  if (hipEventCreate(&r.stop) != hipSuccess) {
+    hipEventDestroy(r.start);
+    return hipErrorOutOfMemory;
+  }
+  hipEventRecord(r.start, p->stream);
+  hipError_t e = launch_pass(A, batch, p->stream);
+  hipEventRecord(r.stop, p->stream);
+  p->recs.push_back(r);
+  return e;
+}
+
+void free_plan(fbp_plan_s* p) {
+  if (!p) return;
+  clear_recs(p);
+  hipFree(p->d_coef);
+  hipFree(p->d_scale);
+  hipFree(p->d_sigma);
+  hipFree(p->d_scratch[0]);
+  hipFree(p->d_scratch[1]);
+  delete p;
+}
+
+int check_batch(const fbp_plan_s* p, int32_t batch) {
+  if (!p) return FBP_EINVAL;
+  if (batch < 0) return FBP_EINVAL;
+  if (batch > p->max_batch) return FBP_ERANGE;
+  return FBP_OK;
+}
+
+PassArgs base_args(const fbp_plan_s* p) {
+  PassArgs A;
+  memset(&A, 0, sizeof(A));
+  A.log2n = p->log2n;
+  A.log2c = p->log2c;
+  A.log2l = p->log2l;
+  A.rs = p->rs;
+  A.groups = p->groups;
+  A.coef_stride = p->coef_stride;
+  A.coef = p->d_coef;
+  A.scale = p->d_scale;
+  A.sigma = p->d_sigma;
+  return A;
+}
+
+// Run the transposed FHT passes.  forward: image -> linogram through the mirrored transform;
+// otherwise linogram -> image (with the filter fused into the first pass when `filter`).
+int run_passes(fbp_plan_s* p, const float* in, float* out, int batch, bool forward,
+               bool filter) {
+  if (batch == 0) return FBP_OK;
+  const int P = (int)p->levels.size();
+  int k = p->log2n;
+  const float* src = in;
+  for (int pi = 0; pi < P; ++pi) {
+    const int F = p->levels[pi];
+    const bool first = pi == 0, last = pi == P - 1;
+    PassArgs A = base_args(p);
+    A.levels = F;
+    A.log2r = F;
+    A.k_hi = k;
+    A.in = src;
+    A.in_mode = (first && forward) ? IN_IMAGE : IN_ROWS;
+    A.order = (first && filter) ? kernel_order(p->order) : 0;
+    hipError_t e;
+    const int kind = forward ? FBP_KERNEL_FORWARD : (first ? FBP_KERNEL_FIRST : FBP_KERNEL_MIDDLE);
+    if (!last) {
+      float* dst = p->d_scratch[pi & 1];
+      A.out = dst;
+      A.out_mode = OUT_ROWS;
+      e = timed_pass(p, A, batch, kind);
+      src = dst;
+    } else if (forward) {
+      A.out = out;
+      A.out_mode = OUT_LINO_MIRROR;
+      e = timed_pass(p, A, batch, kind);
+    } else {
+      A.out = out;
+      A.out_mode = OUT_IMG_V;
+      e = timed_pass(p, A, batch, FBP_KERNEL_LAST_V);
+      if (e == hipSuccess) {
+        A.out_mode = OUT_IMG_H;
+        e = timed_pass(p, A, batch, FBP_KERNEL_LAST_H);
+      }
+    }
+    if (e != hipSuccess) return FBP_EDEVICE;
+    k -= F;
+  }
+  return FBP_OK;
+}
+
+}  // namespace
+
+namespace fhtfbp {
+hipError_t launch_pass(const PassArgs& a, int batch, hipStream_t stream) {
+  switch (a.log2l) {
+    case 2: return launch_pass_l<4>(a, batch, stream);
+    case 3: return launch_pass_l<8>(a, batch, stream);
+    case 4: return launch_pass_l<16>(a, batch, stream);
+    case 5: return launch_pass_l<32>(a, batch, stream);
+    case 6: return launch_pass_l<64>(a, batch, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+}  // namespace fhtfbp
+
+extern "C" {
+
+const char* fbp_strerror(int code) {
+  switch (code) {
+    case FBP_OK: return "ok";
+    case FBP_EINVAL: return "invalid argument";
+    case FBP_EUNSTABLE: return "recursive filter is unstable or has non-finite coefficients";
+    case FBP_ENOMEM: return "device allocation failed";
+    case FBP_EDEVICE: return "HIP runtime or kernel launch failure";
+    case FBP_ERANGE: return "size out of range (batch above max_batch?)";
+    default: return "unknown error";
+  }
+}
+
+int fbp_plan(const fbp_plan_desc* d, fbp_plan_t* out) {
+  if (!out) return FBP_EINVAL;
+  *out = nullptr;
+  if (!d) return FBP_EINVAL;
+  if (!is_pow2(d->n) || d->n < 4 || d->n > 4096) return FBP_EINVAL;
+  if (d->max_batch < 1) return FBP_EINVAL;
+  if (d->order < 1 || d->order > kMaxOrder) return FBP_EINVAL;
+  if (d->groups < 1 || d->groups > 64 || (4 * d->n) % d->groups != 0) return FBP_EINVAL;
+  if (!d->a || !d->b) return FBP_EINVAL;
+  if (d->flags & ~(FBP_NO_ROW_SCALE | FBP_INPUT_IS_FHT | FBP_ZERO_WINDOW)) return FBP_EINVAL;
+  const int K = d->order, G = d->groups;
+  for (int i = 0; i < G * K; ++i)
+    if (!isfinite(d->a[i]) || !isfinite(d->b[i])) return FBP_EUNSTABLE;
+  for (int g = 0; g < G; ++g)
+    if (!stable(d->a + (size_t)g * K, K)) return FBP_EUNSTABLE;
+
+  fbp_plan_s* p = new (std::nothrow) fbp_plan_s();
+  if (!p) return FBP_ENOMEM;
+  p->n = d->n;
+  p->log2n = ilog2(d->n);
+  p->max_batch = d->max_batch;
+  p->order = K;
+  p->groups = G;
+  p->flags = d->flags;
+  p->stream = (hipStream_t)d->stream;
+  p->b.assign(d->b, d->b + (size_t)G * K);
+  p->a.assign(d->a, d->a + (size_t)G * K);
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return FBP_EDEVICE;
+  }
+  // filter chunks: C = min(64, N / 32) chunks of L = N / C samples per row (C = 1, L = N
+  // below N = 32); C never exceeds a wavefront so a row's scan stays in one wave
+  const int N = p->n;
+  const int C = std::max(1, std::min(64, N / 32));
+  p->log2c = ilog2(C);
+  p->log2l = p->log2n - p->log2c;
+  p->rs = N + (N >> p->log2l) + 1;
+  // levels per pass: the tile of 2^F full rows must fit the LDS and 2^F * C <= 1024 threads
+  int lds_max = 0;
+  if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device) !=
+      hipSuccess) {
+    delete p;
+    return FBP_EDEVICE;
+  }
+  lds_max = std::min(lds_max, kLdsBudget);
+  int fmax = 0;
+  for (int F = 1; F <= p->log2n && (1 << F) * C <= 1024; ++F) {
+    PassArgs t;
+    memset(&t, 0, sizeof(t));
+    t.log2n = p->log2n;
+    t.log2r = F;
+    t.log2c = p->log2c;
+    t.levels = F;
+    t.rs = p->rs;
+    if (pass_lds_bytes(t) <= (size_t)lds_max) fmax = F;
+  }
+  if (fmax < 1) {
+    delete p;
+    return FBP_ERANGE;
+  }
+  p->levels = split_levels(p->log2n, fmax);
+  {
+    const int KK = kernel_order(K);
+    p->coef_stride = 2 * KK + kScanLevels * KK * KK;
+  }
+
+  // per-row tables: c_t = k_t w_t (times k_t again for FHT-normalised input), window starts
+  std::vector<float> scale(N);
+  std::vector<int> sigma(N);
+  std::vector<double> th(N);
+  for (int t = 0; t < N; ++t) th[t] = atan((double)t / (double)(N - 1));
+  for (int t = 0; t < N; ++t) {
+    double w;
+    if (t == 0) w = 0.5 * (th[1] - th[0]);
+    else if (t == N - 1) w = 0.5 * (th[N - 1] - th[N - 2]);
+    else w = 0.5 * (th[t + 1] - th[t - 1]);
+    const double m = (double)t / (double)(N - 1);
+    const double k = sqrt(1.0 + m * m);
+    double c = k * w;
+    if (p->flags & FBP_INPUT_IS_FHT) c *= k;
+    if (p->flags & FBP_NO_ROW_SCALE) c = 1.0;
+    scale[t] = (float)c;
+    const int start = (N - 1 - t) / 2 - N / 2;
+    sigma[t] = (p->flags & FBP_ZERO_WINDOW) ? 0 : ((start % N) + N) % N;
+  }
+  const size_t per_class = (size_t)N * N;
+  p->scratch_floats = (size_t)p->max_batch * 4 * per_class;
+  const int nscratch = p->levels.size() >= 3 ? 2 : (p->levels.size() == 2 ? 1 : 0);
+  bool ok = hipMalloc(&p->d_coef, (size_t)G * p->coef_stride * sizeof(float)) == hipSuccess &&
+            hipMalloc(&p->d_scale, N * sizeof(float)) == hipSuccess &&
+            hipMalloc(&p->d_sigma, N * sizeof(int)) == hipSuccess;
+  for (int i = 0; ok && i < nscratch; ++i)
+    ok = hipMalloc(&p->d_scratch[i], p->scratch_floats * sizeof(float)) == hipSuccess;
+  if (!ok) {
+    free_plan(p);
+    return FBP_ENOMEM;
+  }
+  if (hipMemcpy(p->d_scale, scale.data(), N * sizeof(float), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(p->d_sigma, sigma.data(), N * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+    free_plan(p);
+    return FBP_EDEVICE;
+  }
+  int rc = upload_coefficients(p);
+  if (rc != FBP_OK) {
+    free_plan(p);
+    return rc;
+  }
+  *out = p;
+  return FBP_OK;
+}
+
+int fbp_plan_destroy(fbp_plan_t p) {
+  if (!p) return FBP_OK;
+  hipStreamSynchronize(p->stream);
+  free_plan(p);
+  return FBP_OK;
+}
+
+int fbp_plan_set_stream(fbp_plan_t p, void* stream) {
+  if (!p) return FBP_EINVAL;
+  p->stream = (hipStream_t)stream;
+  return FBP_OK;
+}
+
+int fbp_plan_set_coefficients(fbp_plan_t p, const double* b, const double* a) {
+  if (!p || !b || !a) return FBP_EINVAL;
+  const size_t n = (size_t)p->groups * p->order;
+  for (size_t i = 0; i < n; ++i)
+    if (!isfinite(a[i]) || !isfinite(b[i])) return FBP_EUNSTABLE;
+  for (int g = 0; g < p->groups; ++g)
+    if (!stable(a + (size_t)g * p->order, p->order)) return FBP_EUNSTABLE;
+  p->b.assign(b, b + n);
+  p->a.assign(a, a + n);
+  return upload_coefficients(p);
+}
+
+int fbp_plan_profile(fbp_plan_t p, int32_t enable) {
+  if (!p) return FBP_EINVAL;
+  if (enable) clear_recs(p);
+  p->profiling = enable != 0;
+  return FBP_OK;
+}
+
+int fbp_plan_profile_read(fbp_plan_t p, double* total_ms, int32_t* launches) {
+  if (!p || !total_ms || !launches) return FBP_EINVAL;
+  for (int k = 0; k < FBP_KERNEL_KINDS; ++k) {
+    total_ms[k] = 0.0;
+    launches[k] = 0;
+  }
+  int rc = FBP_OK;
+  for (auto& r : p->recs) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.stop) != hipSuccess ||
+        hipEventElapsedTime(&ms, r.start, r.stop) != hipSuccess) {
+      rc = FBP_EDEVICE;
+      continue;
+    }
+    total_ms[r.kind] += ms;
+    launches[r.kind] += 1;
+  }
+  clear_recs(p);
+  return rc;
+}
+
+int fbp_plan_passes(fbp_plan_t p, int32_t* levels, int32_t cap) {
+  if (!p || (cap > 0 && !levels)) return FBP_EINVAL;
+  const int P = (int)p->levels.size();
+  for (int i = 0; i < P && i < cap; ++i) levels[i] = p->levels[i];
+  return P;
+}
+
+int fbp_filter(fbp_plan_t p, const float* in, float* out, int32_t batch) {
+  int rc = check_batch(p, batch);
+  if (rc != FBP_OK) return rc;
+  if (batch == 0) return FBP_OK;
+  if (!in || !out || !aligned16(in) || !aligned16(out)) return FBP_EINVAL;
+  PassArgs A = base_args(p);
+  // tiles of R rows with the plan's chunking: R * C = 1024 threads at most, LDS permitting
+  int log2r = std::min(p->log2n, 10 - p->log2c);
+  while (log2r > 0 && (size_t)(1 << log2r) * p->rs * 4 > (size_t)kLdsBudget) --log2r;
+  A.levels = 0;
+  A.log2r = log2r;
+  A.k_hi = p->log2n;
+  A.in = in;
+  A.out = out;
+  A.in_mode = IN_ROWS;
+  A.out_mode = OUT_SAME;
+  A.order = kernel_order(p->order);
+  return timed_pass(p, A, batch, FBP_KERNEL_FILTER) == hipSuccess ? FBP_OK : FBP_EDEVICE;
+}
+
+int fht_backproject(fbp_plan_t p, const float* lino, float* img, int32_t batch) {
+  int rc = check_batch(p, batch);
+  if (rc != FBP_OK) return rc;
+  if (batch == 0) return FBP_OK;
+  if (!lino || !img || !aligned16(lino) || !aligned16(img)) return FBP_EINVAL;
+  return run_passes(p, lino, img, batch, false, false);
+}
+
+int fbp_reconstruct(fbp_plan_t p, const float* lino, float* img, int32_t batch) {
+  int rc = check_batch(p, batch);
+  if (rc != FBP_OK) return rc;
+  if (batch == 0) return FBP_OK;
+  if (!lino || !img || !aligned16(lino) || !aligned16(img)) return FBP_EINVAL;
+  return run_passes(p, lino, img, batch, false, true);
+}
+
+int fht_forward(fbp_plan_t p, const float* img, float* lino, int32_t batch) {
+  int rc = check_batch(p, batch);
+  if (rc != FBP_OK) return rc;
+  if (batch == 0) return FBP_OK;
+  if (!lino || !img || !aligned16(lino) || !aligned16(img)) return FBP_EINVAL;
+  return run_passes(p, img, lino, batch, true, false);
+}
+
+int fbp_direct_filter(const float* sino, float* work, int32_t batch, int32_t n_angles,
+                      int32_t n_det, void* stream) {
+  if (batch < 0 || n_angles < 1 || n_det < 1 || n_det > 16384) return FBP_EINVAL;
+  if (batch == 0) return FBP_OK;
+  if (!sino || !work) return FBP_EINVAL;
+  const float w = (float)(3.14159265358979323846 / n_angles);
+  return launch_direct_filter(sino, work, batch * n_angles, n_det, w, (hipStream_t)stream) ==
+                 hipSuccess
+             ? FBP_OK
+             : FBP_EDEVICE;
+}
+
+int fbp_direct_backproject(const float* work, float* img, int32_t batch, int32_t n,
+                           int32_t n_angles, int32_t n_det, void* stream) {
+  if (batch < 0 || n < 32 || n % 32 != 0 || n > 8192 || n_angles < 1 || n_det < 1)
+    return FBP_EINVAL;
+  if (batch == 0) return FBP_OK;
+  if (!work || !img) return FBP_EINVAL;
+  return launch_direct_backproject(work, img, batch, n, n_angles, n_det, (hipStream_t)stream) ==
+                 hipSuccess
+             ? FBP_OK
+             : FBP_EDEVICE;
+}
+
+int fbp_direct_parallel(const float* sino, float* work, float* img, int32_t batch, int32_t n,
+                        int32_t n_angles, int32_t n_det, void* stream) {
+  if (batch < 0 || n < 32 || n % 32 != 0 || n > 8192 || n_angles < 1 || n_det < 1 ||
+      n_det > 16384)
+    return FBP_EINVAL;
+  if (batch == 0) return FBP_OK;
+  if (!sino || !work || !img) return FBP_EINVAL;
+  int rc = fbp_direct_filter(sino, work, batch, n_angles, n_det, stream);
+  if (rc != FBP_OK) return rc;
+  return fbp_direct_backproject(work, img, batch, n, n_angles, n_det, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,79 @@
+// Internal declarations shared by the HIP sources of libfhtfbp (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fhtfbp {
+
+constexpr int kMaxOrder = 8;       // largest recursive-filter order supported
+constexpr int kScanLevels = 6;     // chunk transition matrices Phi^(L 2^j), j < 6 (C <= 64)
+constexpr int kMaxPasses = 12;
+constexpr int kLdsBudget = 160 * 1024;
+
+// Where a pass reads its tile rows from.
+enum InMode : int {
+  IN_ROWS = 0,    // rows of a [batch][4][N][N] buffer (linogram or inter-pass scratch)
+  IN_IMAGE = 1,   // forward transform: the class frame of an image, columns mirrored
+};
+
+// Where a pass writes its tile rows to.
+enum OutMode : int {
+  OUT_ROWS = 0,         // next pass's rows of a [batch][4][N][N] buffer, offsets applied
+  OUT_SAME = 1,         // back to the rows it read (filter alone)
+  OUT_IMG_V = 2,        // last back-projection pass, classes 0 and 1 summed into image rows
+  OUT_IMG_H = 3,        // last back-projection pass, classes 2 and 3 transposed, added in
+  OUT_LINO_MIRROR = 4,  // last forward pass: rows with mirrored columns into the linogram
+};
+
+struct PassArgs {
+  const float* in;
+  float* out;
+  int log2n;        // N = 2^log2n
+  int levels;       // butterfly levels done in this pass (0: filter alone)
+  int log2r;        // rows per tile = 2^log2r
+  int k_hi;         // strip height at the start of the pass is 2^k_hi
+  int log2c;        // chunks per row = 2^log2c (filter work items per row)
+  int in_mode;
+  int out_mode;
+  int order;        // recursive filter order K, 0 = no filtering in this pass
+  int groups;       // coefficient groups
+  int coef_stride;  // floats per group in `coef`
+  const float* coef;   // per group: b[K], a[K], Phi_j[K][K] for j < kScanLevels
+  const float* scale;  // [N] row factor c_t
+  const int* sigma;    // [N] window start of row t
+  int rs;              // LDS row stride in floats
+  int log2l;           // chunk length L = 2^log2l
+};
+
+// Launch one pass over `batch` slices on `stream`.  Returns hipSuccess or the launch error.
+// `a.order` is the kernel order: 0 (no filter), 1..4 or 8 (orders 5..7 zero-padded to 8).
+hipError_t launch_pass(const PassArgs& a, int batch, hipStream_t stream);
+template <int L>
+hipError_t launch_pass_l(const PassArgs& a, int batch, hipStream_t stream);
+
+// Kernel order used for a filter of order K.
+inline int kernel_order(int K) { return K <= 4 ? K : kMaxOrder; }
+
+// Whether a pass runs its levels in the streaming form (rows of >= 64 columns, whole waves).
+inline bool pass_streams(const PassArgs& a) {
+  const int threads = (1 << a.log2r) << a.log2c;
+  return a.levels > 0 && a.log2n >= 6 && (threads & 63) == 0;
+}
+
+// LDS bytes of a pass: the tile of 2^log2r skewed rows, plus 64 floats per streaming unit.
+inline size_t pass_lds_bytes(const PassArgs& a) {
+  const size_t tile = (size_t)(1 << a.log2r) * a.rs * sizeof(float);
+  if (!pass_streams(a)) return tile;
+  const int threads = (1 << a.log2r) << a.log2c;
+  const int waves = threads >> 6, pairs = 1 << (a.log2r - 1);
+  return tile + (size_t)(waves > pairs ? waves : pairs) * 64 * sizeof(float);
+}
+
+// Direct FBP comparator kernels.
+hipError_t launch_direct_filter(const float* sino, float* work, int rows, int n_det,
+                                float weight, hipStream_t stream);
+hipError_t launch_direct_backproject(const float* work, float* img, int batch, int n,
+                                     int n_angles, int n_det, hipStream_t stream);
+
+}  // namespace fhtfbp

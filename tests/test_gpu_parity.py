@@ -1,0 +1,261 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Bars: bit-exact on integer data for the Hough transforms (every partial sum stays below 2^24);
+relative RMSE <= 1e-5 for float32 reconstructions and filters against the FP64 oracle.
+Inputs are seeded and synthetic (fbp_inputs); both sides see the same float32 values.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import fbp_inputs as I
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+RTOL_RMSE = 1e-5
+# fixed coefficients (orders 1..8), stable, ramp-like; parity does not depend on their quality
+COEF = {
+    1: ([0.1344], [0.4832]),
+    2: ([0.12372452, -0.12372452], [-0.17164439, -0.13239954]),
+    3: ([0.12496065, -0.22928063, 0.10431998], [-1.02368667, 0.00172808, 0.09470333]),
+    4: ([0.12493199, -0.122976, -0.0727046, 0.07074861],
+        [-0.17279862, -0.72164016, 0.07148985, 0.04270461]),
+}
+
+
+def _coef(order, groups=1, seed=0):
+    if order in COEF and groups == 1:
+        b, a = COEF[order]
+        return np.array(b), np.array(a)
+    g = np.random.default_rng(seed + 31 * order + groups)
+    bs, as_ = [], []
+    for _ in range(groups):
+        poles = g.uniform(-0.8, 0.8, size=order)
+        as_.append(np.poly(poles)[1:])
+        b = g.normal(size=order) * 0.05
+        b[0] = 0.125
+        bs.append(b)
+    return np.array(bs), np.array(as_)
+
+
+def _rel_rmse(got, ref):
+    got = got.detach().cpu().to(torch.float64)
+    ref = ref.to(torch.float64)
+    return float(torch.linalg.vector_norm(got - ref) / torch.linalg.vector_norm(ref))
+
+
+def _phantom_lino(N, B, seed, disc=0.34):
+    d = disc if N >= 64 else 0.25
+    ells = I.random_ellipses(N, 10, seed, disc=d, batch=B)
+    return I.linogram(ells, N).to(torch.float32)
+
+
+# ---- exact integer Hough transforms --------------------------------------------------------
+
+@pytest.mark.parametrize("N,B", [(4, 1), (8, 2), (16, 3), (32, 2), (64, 2), (128, 3), (256, 2),
+                                 (512, 2), (1024, 1), (2048, 1)])
+def test_backproject_integer_bit_exact(gpu_lib, N, B):
+    api = gpu_lib
+    P = I.random_int_array((B, 4, N, N), 0, 1000, seed=N + B).to(torch.float32)
+    with api.fbp_plan(N, B, *_coef(2)) as plan:
+        got = api.fht_backproject(plan, P.cuda())
+        torch.cuda.synchronize()
+    ref = O.fht_backproject(P.to(torch.float64))
+    assert torch.equal(got.cpu().to(torch.float64), ref)
+
+
+@pytest.mark.parametrize("N,B", [(4, 1), (16, 2), (64, 3), (256, 1), (1024, 1), (2048, 1)])
+def test_forward_integer_bit_exact(gpu_lib, N, B):
+    api = gpu_lib
+    f = I.random_int_array((B, N, N), 0, 1000, seed=7 * N + B).to(torch.float32)
+    with api.fbp_plan(N, B, *_coef(2)) as plan:
+        got = api.fht_forward(plan, f.cuda())
+        torch.cuda.synchronize()
+    ref = O.fht_forward(f.to(torch.float64))
+    assert torch.equal(got.cpu().to(torch.float64), ref)
+
+
+@pytest.mark.parametrize("N", [2048])
+def test_adjoint_identity_on_gpu(gpu_lib, N):
+    api = gpu_lib
+    x = I.random_int_array((1, N, N), 0, 1000, seed=1).to(torch.float32).cuda()
+    y = I.random_int_array((1, 4, N, N), 0, 1000, seed=2).to(torch.float32).cuda()
+    with api.fbp_plan(N, 1, *_coef(2)) as plan:
+        hx = api.fht_forward(plan, x)
+        hty = api.fht_backproject(plan, y)
+        torch.cuda.synchronize()
+    lhs = (hx.double() * y.double()).sum().item()
+    rhs = (x.double() * hty.double()).sum().item()
+    assert lhs == rhs
+
+
+# ---- recursive filter ------------------------------------------------------------------------
+
+@pytest.mark.parametrize("N,order,groups", [(32, 2, 1), (64, 1, 1), (128, 2, 1), (256, 3, 1),
+                                            (256, 4, 8), (512, 5, 1), (1024, 2, 1),
+                                            (1024, 4, 8), (2048, 2, 1), (128, 8, 4),
+                                            (64, 6, 2), (128, 7, 1), (16, 2, 1), (8, 3, 1)])
+def test_filter_matches_oracle(gpu_lib, N, order, groups):
+    api = gpu_lib
+    B = 2
+    P = torch.randn(B, 4, N, N, generator=torch.Generator().manual_seed(N + order),
+                    dtype=torch.float64).to(torch.float32)
+    b, a = _coef(order, groups)
+    with api.fbp_plan(N, B, b, a) as plan:
+        got = api.fbp_filter(plan, P.cuda())
+        torch.cuda.synchronize()
+    ref = O.filter_linogram(P.to(torch.float64), torch.tensor(b), torch.tensor(a))
+    assert _rel_rmse(got, ref) < RTOL_RMSE
+
+
+@pytest.mark.parametrize("flags", [1, 2, 4, 6])
+def test_filter_flags(gpu_lib, flags):
+    api = gpu_lib
+    N, B = 128, 1
+    P = torch.randn(B, 4, N, N, generator=torch.Generator().manual_seed(flags),
+                    dtype=torch.float64).to(torch.float32)
+    b, a = _coef(2)
+    with api.fbp_plan(N, B, b, a, flags=flags) as plan:
+        got = api.fbp_filter(plan, P.cuda())
+        torch.cuda.synchronize()
+    ref = O.filter_linogram(P.to(torch.float64), torch.tensor(b), torch.tensor(a),
+                            scale=not (flags & 1), input_is_fht=bool(flags & 2),
+                            windowed=not (flags & 4))
+    assert _rel_rmse(got, ref) < RTOL_RMSE
+
+
+def test_filter_in_place(gpu_lib):
+    api = gpu_lib
+    N, B = 256, 2
+    P = _phantom_lino(N, B, 5)
+    b, a = _coef(2)
+    with api.fbp_plan(N, B, b, a) as plan:
+        x = P.cuda()
+        api.fbp_filter(plan, x, x)
+        torch.cuda.synchronize()
+    ref = O.filter_linogram(P.to(torch.float64), torch.tensor(b), torch.tensor(a))
+    assert _rel_rmse(x, ref) < RTOL_RMSE
+
+
+# ---- the method end to end ------------------------------------------------------------------
+
+@pytest.mark.parametrize("N,B,order", [(8, 1, 2), (16, 2, 2), (32, 2, 2), (64, 2, 3),
+                                       (128, 3, 2), (256, 2, 2), (512, 2, 4), (1024, 2, 2),
+                                       (2048, 1, 2)])
+def test_reconstruct_matches_oracle(gpu_lib, N, B, order):
+    api = gpu_lib
+    P = _phantom_lino(N, B, seed=N)
+    b, a = _coef(order)
+    with api.fbp_plan(N, B, b, a) as plan:
+        got = api.fbp_reconstruct(plan, P.cuda())
+        torch.cuda.synchronize()
+    ref = O.fbp_fht(P.to(torch.float64), torch.tensor(b), torch.tensor(a))
+    assert _rel_rmse(got, ref) < RTOL_RMSE
+
+
+def test_reconstruct_equals_filter_then_backproject(gpu_lib):
+    api = gpu_lib
+    N, B = 512, 2
+    P = _phantom_lino(N, B, 9).cuda()
+    with api.fbp_plan(N, B, *_coef(3)) as plan:
+        fused = api.fbp_reconstruct(plan, P)
+        split = api.fht_backproject(plan, api.fbp_filter(plan, P))
+        torch.cuda.synchronize()
+    assert _rel_rmse(fused, split.cpu().double()) < 1e-6
+
+
+def test_reconstruct_grouped_coefficients(gpu_lib):
+    api = gpu_lib
+    N, B = 256, 2
+    P = _phantom_lino(N, B, 11)
+    b, a = _coef(4, groups=8)
+    with api.fbp_plan(N, B, b, a) as plan:
+        got = api.fbp_reconstruct(plan, P.cuda())
+        torch.cuda.synchronize()
+    ref = O.fbp_fht(P.to(torch.float64), torch.tensor(b), torch.tensor(a))
+    assert _rel_rmse(got, ref) < RTOL_RMSE
+
+
+def test_full_size_batch_sampled_parity(gpu_lib):
+    """512 slices of N = 1024 (the benchmark's launch configuration); two slices checked."""
+    api = gpu_lib
+    N, B = 1024, 512
+    lino, _ = I.volume_linogram(N, B, count=30, seed=3, device="cuda")
+    b, a = _coef(2)
+    with api.fbp_plan(N, B, b, a) as plan:
+        img = api.fbp_reconstruct(plan, lino)
+        torch.cuda.synchronize()
+    for s in (0, 301):
+        ref = O.fbp_fht(lino[s].cpu().to(torch.float64), torch.tensor(b), torch.tensor(a))
+        assert _rel_rmse(img[s], ref) < RTOL_RMSE
+
+
+# ---- edge cases and errors ----------------------------------------------------------------
+
+def test_empty_batch_and_errors(gpu_lib):
+    api = gpu_lib
+    N = 64
+    with api.fbp_plan(N, 2, *_coef(2)) as plan:
+        z = torch.empty(0, 4, N, N, device="cuda")
+        out = api.fbp_reconstruct(plan, z)
+        assert out.shape == (0, N, N)
+        with pytest.raises(api.FbpError) as e:
+            api.fbp_reconstruct(plan, torch.zeros(3, 4, N, N, device="cuda"))
+        assert e.value.code == -5
+        with pytest.raises(ValueError):
+            api.fbp_reconstruct(plan, torch.zeros(1, 4, N, N, device="cuda", dtype=torch.float64))
+        with pytest.raises(ValueError):
+            api.fbp_reconstruct(plan, torch.zeros(1, 4, N, N))
+    with pytest.raises(api.FbpError) as e:
+        api.fbp_plan(N, 1, [0.1, 0.1], [0.0, 1.5])
+    assert e.value.code == -2
+
+
+def test_plan_pass_structure(gpu_lib):
+    api = gpu_lib
+    expect = {4: [2], 64: [6], 128: [7], 256: [4, 4], 512: [4, 5], 1024: [5, 5],
+              2048: [3, 4, 4], 4096: [3, 3, 3, 3]}
+    for N, lv in expect.items():
+        with api.fbp_plan(N, 1, *_coef(2)) as plan:
+            assert plan.passes() == lv
+
+
+def test_max_size_4096(gpu_lib):
+    api = gpu_lib
+    N = 4096
+    P = I.random_int_array((1, 4, N, N), 0, 250, seed=4096).to(torch.float32)
+    with api.fbp_plan(N, 1, *_coef(2)) as plan:
+        got = api.fht_backproject(plan, P.cuda())
+        torch.cuda.synchronize()
+    # sampled rows against the definition: image row y = sum over classes and slopes
+    D = O.dyadic_shift(N)
+    Pd = P[0].to(torch.float64)
+    x = torch.arange(N)
+    for y in (0, 1234, 4095):
+        ref = torch.zeros(N, dtype=torch.float64)
+        # class 0 contributes sum_t P0[t][(x - D[t,y]) mod N]; class 1 mirrored in x
+        idx = (x[None, :] - D[:, y][:, None]) % N
+        ref += torch.gather(Pd[0], 1, idx).sum(0)
+        ref += torch.gather(Pd[1], 1, idx).sum(0).flip(0)
+        # classes 2, 3 contribute through the transpose: image[y][x] gets FHT^T(P2)[x][y]
+        idxT = (y - D[:, x]) % N                      # [t, x]
+        ref += torch.gather(Pd[2], 1, idxT).sum(0)
+        idx3 = ((N - 1 - y) - D[:, x]) % N
+        ref += torch.gather(Pd[3], 1, idx3).sum(0)
+        assert torch.equal(got[0, y].cpu().to(torch.float64), ref)
+
+
+# ---- direct FBP comparator ------------------------------------------------------------------
+
+@pytest.mark.parametrize("N,P", [(64, 256), (128, 512)])
+def test_direct_fbp_comparator_matches_oracle(gpu_lib, N, P):
+    api = gpu_lib
+    ells = I.random_ellipses(N, 10, seed=N)
+    sino = I.parallel_sinogram(ells, N, P).to(torch.float32)
+    got = api.fbp_direct_parallel(sino[None].cuda(), N)
+    torch.cuda.synchronize()
+    ref = O.fbp_direct_parallel(sino.to(torch.float64), N)
+    assert _rel_rmse(got[0], ref) < 1e-4

@@ -38,7 +38,21 @@ def parse():
     ap.add_argument("--no-direct", action="store_true", help="skip the direct-FBP comparator")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-slices", type=int, default=16)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 5 times (for scaling the "
+                         "FETCH_SIZE / WRITE_SIZE counters) and exit")
     return ap.parse_args()
+
+
+def copy_calibration():
+    import torch
+    n = 1 << 28                                   # 2^28 floats = 1 GiB each way
+    src = torch.ones(n, device="cuda", dtype=torch.float32)
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_each_way": n * 4, "launches": 5}))
 
 
 def algorithmic_bytes(kind: str, n: int, levels: list[int]) -> float:
@@ -75,6 +89,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     import torch
     import fbp_inputs as I
     import paper_2007_06289_amd as F

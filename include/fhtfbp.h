@@ -57,7 +57,8 @@ typedef struct {
                          divide 4N and be <= 64                                               */
   const double* b;    /* host [groups][order]: feed-forward b_0..b_{K-1} (eq 9); the causal
                          and the anticausal pass share them (Sec. 3)                          */
-  const double* a;    /* host [groups][order]: feedback a_1..a_K (eq 9)                        */
+  const double* a;    /* host [groups][order]: feedback a_1..a_K (eq 9).  The kernels hold b
+                         and a as float32 (rounded to nearest on upload)                       */
   uint32_t flags;     /* FBP_* flags above                                                    */
   void* stream;       /* hipStream_t used by every call (NULL = default stream)               */
 } fbp_plan_desc;

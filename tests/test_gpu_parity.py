@@ -27,6 +27,16 @@ COEF = {
 
 
 def _coef(order, groups=1, seed=0):
+    """Coefficients as the kernels hold them (float32 values, returned as float64), so both
+    sides run the same filter.  The reconstruction is very sensitive to the filter's response
+    at zero frequency (sum of b): rounding an exactly balanced b to float32 moves it by ~1e-8,
+    which the back projection amplifies by ~N; that is a property of the method's parameters,
+    not of the kernels, and is measured separately below."""
+    b, a = _coef64(order, groups, seed)
+    return b.astype(np.float32).astype(np.float64), a.astype(np.float32).astype(np.float64)
+
+
+def _coef64(order, groups=1, seed=0):
     if order in COEF and groups == 1:
         b, a = COEF[order]
         return np.array(b), np.array(a)
@@ -154,6 +164,24 @@ def test_reconstruct_matches_oracle(gpu_lib, N, B, order):
         torch.cuda.synchronize()
     ref = O.fbp_fht(P.to(torch.float64), torch.tensor(b), torch.tensor(a))
     assert _rel_rmse(got, ref) < RTOL_RMSE
+
+
+def test_coefficient_rounding_sensitivity(gpu_lib):
+    """With exact (FP64) coefficients in the oracle, order 2 still meets the bar because its
+    balanced pair b = (b0, -b0) is exact in float32; order 4 shows the DC sensitivity."""
+    api = gpu_lib
+    N, B = 512, 1
+    P = _phantom_lino(N, B, seed=N)
+    errs = {}
+    for order in (2, 4):
+        b64, a64 = _coef64(order)
+        with api.fbp_plan(N, B, b64, a64) as plan:
+            got = api.fbp_reconstruct(plan, P.cuda())
+            torch.cuda.synchronize()
+        ref = O.fbp_fht(P.to(torch.float64), torch.tensor(b64), torch.tensor(a64))
+        errs[order] = _rel_rmse(got, ref)
+    assert errs[2] < RTOL_RMSE
+    assert errs[4] < 2e-4
 
 
 def test_reconstruct_equals_filter_then_backproject(gpu_lib):

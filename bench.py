@@ -105,7 +105,7 @@ def main():
     print(f"[bench] fit order {args.order}: rel err {fit_err:.4f}", file=sys.stderr, flush=True)
 
     t0 = time.perf_counter()
-    lino, slices = I.volume_linogram(N, B, count=30, seed=3, device=dev)
+    lino, slices = I.volume_linogram(N, B, count=30, seed=3, device=dev, chunk=32)
     torch.cuda.synchronize()
     print(f"[bench] generated {B} x 4 x {N}^2 linogram in {time.perf_counter() - t0:.1f} s",
           file=sys.stderr, flush=True)

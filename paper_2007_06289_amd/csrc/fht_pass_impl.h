@@ -84,10 +84,13 @@ __device__ void load_tile(const PassArgs& A, float* S, int b, int q, int row0) {
 // the recursion from zero state, the true entering states come from a scan over the chunks of
 // the row (lanes of one wave) with the transition matrices Phi^(L 2^j), and the response of
 // the recursion to that entering state is added.  The anticausal pass is the same recursion
-// run from the end of the window.
+// run from the end of the window.  Inputs are re-read from LDS in each sweep (only a K-sample
+// sliding window is held), the output of the chunk is accumulated in registers.
 template <int L, int K>
 __device__ void filter_tile(const PassArgs& A, float* S, int q, int row0) {
-  const int tid = threadIdx.x;
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));   // recomputed per call (keeps loop-invariant addresses out of
+                                  // registers in the persistent kernel)
   const int C = 1 << A.log2c;
   const int r = tid >> A.log2c, c = tid & (C - 1);
   const int N = 1 << A.log2n, mask = N - 1;
@@ -101,36 +104,40 @@ __device__ void filter_tile(const PassArgs& A, float* S, int q, int row0) {
     ak[k] = cf[K + k];
   }
   const float* phi = cf + 2 * K;
-  const int sig = A.sigma[t];
+  int sig = A.sigma[t];
   const float ct = A.scale[t];
   const int base = c * L;
   float* row = S + r * A.rs;
-  auto at = [&](int i) -> float {   // window position i -> LDS value
+  const int log2l = A.log2l;
+  auto in = [&](int i) -> float {   // window position i (inside the window) -> LDS value
     const int s = (sig + i) & mask;
-    return row[s + (s >> A.log2l)];
+    return row[s + (s >> log2l)];
   };
-  float x[L];
-#pragma unroll
-  for (int i = 0; i < L; ++i) x[i] = at(base + i);
-  float xp[K], xn[K];   // window samples before / after the chunk (zero outside the window)
-#pragma unroll
-  for (int k = 1; k < K; ++k) {
-    xp[k] = (base - k >= 0) ? at(base - k) : 0.f;
-    xn[k] = (base + L - 1 + k < N) ? at(base + L - 1 + k) : 0.f;
-  }
-  xp[0] = 0.f;
-  xn[0] = 0.f;
+  auto at = [&](int i) -> float {   // halo sample: zero outside the window
+    const int s = (sig + ((i < 0 || i >= N) ? 0 : i)) & mask;
+    const float v = row[s + (s >> log2l)];
+    return (i >= 0 && i < N) ? v : 0.f;
+  };
 
   float y[L];
-  float st[K];
+  float st[K], xs[K];   // recursion state (y[i-1], ...), input window (x[i], x[i-1], ...)
   // causal pass, zero entering state
+  asm volatile("" : "+v"(sig));
+  // each step shifts the window up by one and puts the new sample in xs[0], so xs[m] starts as
+  // the sample m + 1 positions before the chunk
 #pragma unroll
-  for (int k = 0; k < K; ++k) st[k] = 0.f;
+  for (int k = 0; k < K; ++k) {
+    st[k] = 0.f;
+    xs[k] = (k < K - 1) ? at(base - 1 - k) : 0.f;
+  }
 #pragma unroll
   for (int i = 0; i < L; ++i) {
+#pragma unroll
+    for (int k = K - 1; k > 0; --k) xs[k] = xs[k - 1];
+    xs[0] = in(base + i);
     float acc = 0.f;
 #pragma unroll
-    for (int k = 0; k < K; ++k) acc = fmaf(bk[k], (i - k >= 0) ? x[i - k] : xp[k - i], acc);
+    for (int k = 0; k < K; ++k) acc = fmaf(bk[k], xs[k], acc);
 #pragma unroll
     for (int k = 0; k < K; ++k) acc = fmaf(-ak[k], st[k], acc);
     y[i] = acc;
@@ -138,7 +145,8 @@ __device__ void filter_tile(const PassArgs& A, float* S, int q, int row0) {
     for (int k = K - 1; k > 0; --k) st[k] = st[k - 1];
     st[0] = acc;
   }
-  // inclusive scan of the end states over the chunks to the left
+  // inclusive scan of the end states over the chunks to the left, then the response of the
+  // recursion to the entering state
   {
     float tv[K];
 #pragma unroll
@@ -159,33 +167,39 @@ __device__ void filter_tile(const PassArgs& A, float* S, int q, int row0) {
         }
       }
     }
-    float sin_[K];
+    // every lane takes part in the shuffle (a lane reading an inactive lane gets nothing)
 #pragma unroll
-    for (int k = 0; k < K; ++k) sin_[k] = (C > 1) ? __shfl_up(tv[k], 1, C) : 0.f;
+    for (int k = 0; k < K; ++k) st[k] = (C > 1) ? __shfl_up(tv[k], 1, C) : 0.f;
     if (c == 0) {
 #pragma unroll
-      for (int k = 0; k < K; ++k) sin_[k] = 0.f;
+      for (int k = 0; k < K; ++k) st[k] = 0.f;
     }
-    // response of the recursion to the entering state
 #pragma unroll
     for (int i = 0; i < L; ++i) {
       float z = 0.f;
 #pragma unroll
-      for (int k = 0; k < K; ++k) z = fmaf(-ak[k], sin_[k], z);
+      for (int k = 0; k < K; ++k) z = fmaf(-ak[k], st[k], z);
       y[i] += z;
 #pragma unroll
-      for (int k = K - 1; k > 0; --k) sin_[k] = sin_[k - 1];
-      sin_[0] = z;
+      for (int k = K - 1; k > 0; --k) st[k] = st[k - 1];
+      st[0] = z;
     }
   }
   // anticausal pass, zero entering state, added into y as it goes
+  asm volatile("" : "+v"(sig));
 #pragma unroll
-  for (int k = 0; k < K; ++k) st[k] = 0.f;
+  for (int k = 0; k < K; ++k) {
+    st[k] = 0.f;
+    xs[k] = (k < K - 1) ? at(base + L + k) : 0.f;
+  }
 #pragma unroll
   for (int i = L - 1; i >= 0; --i) {
+#pragma unroll
+    for (int k = K - 1; k > 0; --k) xs[k] = xs[k - 1];
+    xs[0] = in(base + i);
     float acc = 0.f;
 #pragma unroll
-    for (int k = 0; k < K; ++k) acc = fmaf(bk[k], (i + k < L) ? x[i + k] : xn[i + k - L + 1], acc);
+    for (int k = 0; k < K; ++k) acc = fmaf(bk[k], xs[k], acc);
 #pragma unroll
     for (int k = 0; k < K; ++k) acc = fmaf(-ak[k], st[k], acc);
     y[i] += acc;
@@ -213,29 +227,29 @@ __device__ void filter_tile(const PassArgs& A, float* S, int q, int row0) {
         }
       }
     }
-    float sin_[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) sin_[k] = (C > 1) ? __shfl_down(tv[k], 1, C) : 0.f;
+    for (int k = 0; k < K; ++k) st[k] = (C > 1) ? __shfl_down(tv[k], 1, C) : 0.f;
     if (c == C - 1) {
 #pragma unroll
-      for (int k = 0; k < K; ++k) sin_[k] = 0.f;
+      for (int k = 0; k < K; ++k) st[k] = 0.f;
     }
 #pragma unroll
     for (int i = L - 1; i >= 0; --i) {
       float z = 0.f;
 #pragma unroll
-      for (int k = 0; k < K; ++k) z = fmaf(-ak[k], sin_[k], z);
+      for (int k = 0; k < K; ++k) z = fmaf(-ak[k], st[k], z);
       y[i] += z;
 #pragma unroll
-      for (int k = K - 1; k > 0; --k) sin_[k] = sin_[k - 1];
-      sin_[0] = z;
+      for (int k = K - 1; k > 0; --k) st[k] = st[k - 1];
+      st[0] = z;
     }
   }
   __syncthreads();   // every chunk has read its samples and its neighbours' halo
+  asm volatile("" : "+v"(sig));
 #pragma unroll
   for (int i = 0; i < L; ++i) {
     const int s = (sig + base + i) & mask;
-    row[s + (s >> A.log2l)] = ct * y[i];
+    row[s + (s >> log2l)] = ct * y[i];
   }
   __syncthreads();
 }
@@ -273,22 +287,113 @@ __device__ __forceinline__ void level_stream(const PassArgs& A, float* S, float*
     float* row0 = S + r0 * A.rs;
     float* row1 = S + r1 * A.rs;
     const int x0 = seg * W;
-    for (int blk = (W >> 6) - 1; blk >= 0; --blk) {
-      const int x = x0 + (blk << 6) + lane;
-      const int x1 = x - J, x2 = x - J - 1;
-      const float v0 = row0[x + (x >> A.log2l)];
-      float v1, v2;
-      if (blk > 0) {
-        v1 = row1[x1 + (x1 >> A.log2l)];
-        v2 = row1[x2 + (x2 >> A.log2l)];
-      } else {
-        // columns below x0 come from the copy (entry k holds column x0 - 64 + k)
-        const int m1 = x1 & mask, m2 = x2 & mask;
-        v1 = (x1 >= x0) ? row1[m1 + (m1 >> A.log2l)] : below[unit * 64 + ((x1 - x0 + 64) & 63)];
-        v2 = (x2 >= x0) ? row1[m2 + (m2 >> A.log2l)] : below[unit * 64 + ((x2 - x0 + 64) & 63)];
+    // blocks from the top; the reads of a lower block never touch columns a higher block of
+    // the same batch writes, so four blocks are read before any is written
+    for (int top = (W >> 6) - 1; top >= 0; top -= 4) {
+      float va[4], vb[4];
+#pragma unroll
+      for (int u2 = 0; u2 < 4; ++u2) {
+        const int blk = top - u2;
+        if (blk < 0) break;
+        const int x = x0 + (blk << 6) + lane;
+        const int x1 = x - J, x2 = x - J - 1;
+        const float v0 = row0[x + (x >> A.log2l)];
+        float v1, v2;
+        if (blk > 0) {
+          v1 = row1[x1 + (x1 >> A.log2l)];
+          v2 = row1[x2 + (x2 >> A.log2l)];
+        } else {
+          // columns below x0 come from the copy (entry k holds column x0 - 64 + k)
+          const int m1 = x1 & mask, m2 = x2 & mask;
+          v1 = (x1 >= x0) ? row1[m1 + (m1 >> A.log2l)] : below[unit * 64 + ((x1 - x0 + 64) & 63)];
+          v2 = (x2 >= x0) ? row1[m2 + (m2 >> A.log2l)] : below[unit * 64 + ((x2 - x0 + 64) & 63)];
+        }
+        va[u2] = v0 + v1;
+        vb[u2] = v0 + v2;
       }
-      row0[x + (x >> A.log2l)] = v0 + v1;
-      row1[x + (x >> A.log2l)] = v0 + v2;
+#pragma unroll
+      for (int u2 = 0; u2 < 4; ++u2) {
+        const int blk = top - u2;
+        if (blk < 0) break;
+        const int x = x0 + (blk << 6) + lane;
+        row0[x + (x >> A.log2l)] = va[u2];
+        row1[x + (x >> A.log2l)] = vb[u2];
+      }
+    }
+  }
+}
+
+// Streaming level with a compile-time number of 64-column blocks per unit and the 32-column
+// skew: the five LDS addresses of a butterfly are per-unit base pointers plus immediate offsets
+// (66 words per block), so the walk costs two adds per 64 butterflies besides the LDS accesses.
+template <int NBLK>
+__device__ __forceinline__ void level_stream_fast(const PassArgs& A, float* S, float* below,
+                                                  int l) {
+  const int N = 1 << A.log2n, mask = N - 1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int waves = blockDim.x >> 6;
+  const int log2p = A.log2r - 1;
+  const int segs = waves > (1 << log2p) ? waves >> log2p : 1;
+  constexpr int W = NBLK * 64;
+  const int units = ((1 << log2p) * segs) / waves;
+  for (int u = 0; u < units; ++u) {
+    const int unit = wave + u * waves;
+    const int pair = unit / segs, seg = unit - pair * segs;
+    const int ib = pair & ((1 << l) - 1), pp = pair >> l;
+    const int r1 = ((pp << (l + 1)) | ib) | (1 << l);
+    const int xb = (seg * W - 64 + lane) & mask;
+    below[unit * 64 + lane] = S[r1 * A.rs + xb + (xb >> 5)];
+  }
+  __syncthreads();
+  for (int u = 0; u < units; ++u) {
+    const int unit = wave + u * waves;
+    const int pair = unit / segs, seg = unit - pair * segs;
+    const int ib = pair & ((1 << l) - 1), pp = pair >> l;
+    const int r0 = (pp << (l + 1)) | ib, r1 = r0 | (1 << l);
+    const int J = brev_bits(ib, l);
+    float* row0 = S + r0 * A.rs;
+    float* row1 = S + r1 * A.rs;
+    const int x0 = seg * W;
+    const int xb = x0 + 64 + lane;              // column of block 1
+    const int x1 = xb - J, x2 = xb - J - 1;     // >= 0 since J < 64
+    float* a0 = row0 + xb + (xb >> 5);
+    float* w1 = row1 + xb + (xb >> 5);
+    const float* a1 = row1 + x1 + (x1 >> 5);
+    const float* a2 = row1 + x2 + (x2 >> 5);
+#pragma unroll
+    for (int top = NBLK - 1; top >= 1; top -= 4) {
+      float va[4], vb[4];
+#pragma unroll
+      for (int u2 = 0; u2 < 4; ++u2) {
+        const int k = top - u2;
+        if (k >= 1) {
+          const int off = 66 * (k - 1);
+          const float v0 = a0[off];
+          va[u2] = v0 + a1[off];
+          vb[u2] = v0 + a2[off];
+        }
+      }
+#pragma unroll
+      for (int u2 = 0; u2 < 4; ++u2) {
+        const int k = top - u2;
+        if (k >= 1) {
+          const int off = 66 * (k - 1);
+          a0[off] = va[u2];
+          w1[off] = vb[u2];
+        }
+      }
+    }
+    {   // block 0: reads below x0 come from the copy
+      const int x = x0 + lane;
+      const int y1 = x - J, y2 = x - J - 1;
+      const int m1 = y1 & mask, m2 = y2 & mask;
+      const float v0 = row0[x + (x >> 5)];
+      const float t1 = row1[m1 + (m1 >> 5)];
+      const float t2 = row1[m2 + (m2 >> 5)];
+      const float v1 = (y1 >= x0) ? t1 : below[unit * 64 + ((y1 - x0 + 64) & 63)];
+      const float v2 = (y2 >= x0) ? t2 : below[unit * 64 + ((y2 - x0 + 64) & 63)];
+      row0[x + (x >> 5)] = v0 + v1;
+      row1[x + (x >> 5)] = v0 + v2;
     }
   }
 }
@@ -456,6 +561,275 @@ __global__ void __launch_bounds__(1024) fht_combine_kernel(PassArgs A) {
   }
 }
 
+// ---- persistent first pass: filter + top levels, the next tile's rows prefetched ------------
+// Each block loops over tiles (b, q, v) with a stride of the grid; the global loads of the next
+// tile are issued into registers after the current tile is filtered, so they are in flight
+// while the current tile's levels run and it is written out.
+template <int L, int K, int NBLK>
+__global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
+  extern __shared__ float S[];
+  const int T = blockDim.x, tid = threadIdx.x;
+  const int N = 1 << A.log2n, mask = N - 1;
+  const int F = A.levels;
+  const int tiles = N >> A.log2r;            // tiles per class (first pass: j = 0, tile = v)
+  const int k_lo = A.k_hi - F;
+  constexpr int NV = (L / 4 > 0) ? L / 4 : 1;   // float4 per thread per tile
+  float4 pre[NV];
+  int tl = blockIdx.x;
+  if (tl >= A.total_tiles) return;
+  auto issue = [&](int t2) {
+    const int bq = t2 / tiles, v = t2 - bq * tiles;
+    const float4* src = reinterpret_cast<const float4*>(A.in + ((size_t)bq * N + (v << F)) * N);
+#pragma unroll
+    for (int k = 0; k < NV; ++k) pre[k] = src[tid + k * T];
+  };
+  issue(tl);
+  for (; tl < A.total_tiles; tl += gridDim.x) {
+    // the thread index is passed through an empty asm once per tile, so per-thread addresses
+    // are recomputed each iteration instead of being held in registers across the whole loop
+    int ltid = tid;
+    asm volatile("" : "+v"(ltid));
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const int e4 = (ltid + k * T) << 2;
+      const int r = e4 >> A.log2n, x = e4 & mask;
+      float* d = S + r * A.rs;
+      d[x + (x >> A.log2l)] = pre[k].x;
+      d[x + 1 + ((x + 1) >> A.log2l)] = pre[k].y;
+      d[x + 2 + ((x + 2) >> A.log2l)] = pre[k].z;
+      d[x + 3 + ((x + 3) >> A.log2l)] = pre[k].w;
+    }
+    __syncthreads();
+    const int bq = tl / tiles, v = tl - bq * tiles;
+    const int q = bq & 3;
+    const int row0 = v << F;
+    if constexpr (K > 0) filter_tile<L, K>(A, S, q, row0);
+    // the next tile's loads fly during the levels and the write-out of this one
+    asm volatile("" ::: "memory");
+    if (tl + (int)gridDim.x < A.total_tiles) issue(tl + gridDim.x);
+    {
+      float* below = S + (1 << A.log2r) * A.rs;
+      for (int l = 0; l < F; ++l) {
+        level_stream_fast<NBLK>(A, S, below, l);
+        __syncthreads();
+      }
+    }
+    float* dst = A.out + (size_t)bq * N * N;
+    int stid = tid;
+    asm volatile("" : "+v"(stid));
+    for (int e = stid; e < (N << F) >> 2; e += T) {
+      const int rho = (e << 2) >> A.log2n, x = (e << 2) & mask;
+      const int i = brev_bits(rho, F);
+      const int orow = (i << k_lo) + v;
+      const int o = (v * i) & mask;
+      float4 w;
+      w.x = S[lds_at(rho, (x - o) & mask, A.rs, A.log2l)];
+      w.y = S[lds_at(rho, (x + 1 - o) & mask, A.rs, A.log2l)];
+      w.z = S[lds_at(rho, (x + 2 - o) & mask, A.rs, A.log2l)];
+      w.w = S[lds_at(rho, (x + 3 - o) & mask, A.rs, A.log2l)];
+      *reinterpret_cast<float4*>(dst + (size_t)orow * N + x) = w;
+    }
+    __syncthreads();
+  }
+}
+
+// ---- column-tiled passes (no filter) ---------------------------------------------------------
+// With lazy shifts, an output column of a pass depends only on the 2^F - 1 columns below it, so a
+// tile can be a column block of W = 2^log2w columns plus a halo of `halo` columns below it, with
+// no wrap-around inside the tile.  NCLS = 2 (last back-projection pass): the block holds the
+// matching column blocks of a class pair and sums them into the image.  NCLS = 1 (middle pass):
+// one class, rows written with their pending rotation.
+__device__ __forceinline__ int cat(int r, int c, int rs) { return r * rs + c + (c >> 5); }
+
+__device__ void cols_load(const PassArgs& A, float* S, int rs, const float* cls, int row0,
+                          int xs) {
+  const int N = 1 << A.log2n, mask = N - 1;
+  const int R = 1 << A.log2r;
+  const int wt = (1 << A.log2w) + A.halo;
+  const int nv = wt >> 2;                      // float4 per row
+  for (int e = threadIdx.x; e < R * nv; e += blockDim.x) {
+    const int r = e / nv, c4 = (e - r * nv) << 2;
+    const float4 v = *reinterpret_cast<const float4*>(cls + (size_t)(row0 + r) * N +
+                                                       ((xs + c4) & mask));
+    float* d = S + r * rs;
+    d[c4 + (c4 >> 5)] = v.x;
+    d[c4 + 1 + ((c4 + 1) >> 5)] = v.y;
+    d[c4 + 2 + ((c4 + 2) >> 5)] = v.z;
+    d[c4 + 3 + ((c4 + 3) >> 5)] = v.w;
+  }
+}
+
+// One level on all units (class, row pair) of the block; walks each unit's columns from the
+// top in batches of four 64-column blocks (reads before writes).  Columns below J + 1 are left
+// as they are (they only feed outputs below the halo).
+__device__ void cols_level(float* S, int rs, int log2r, int ncls, int wt, int l) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
+  const int pairs = 1 << (log2r - 1);
+  const int units = ncls * pairs;
+  const int R = 1 << log2r;
+  const int nblk = (wt + 63) >> 6;
+  const int pad = (nblk << 6) - wt;       // block bb covers columns bb * 64 - pad + lane
+  for (int unit = wave; unit < units; unit += waves) {
+    const int cls = unit / pairs, pair = unit - cls * pairs;
+    const int ib = pair & ((1 << l) - 1), pp = pair >> l;
+    const int r0 = (pp << (l + 1)) | ib, r1 = r0 | (1 << l);
+    const int J = brev_bits(ib, l);
+    float* base = S + cls * R * rs;
+    for (int top = nblk - 1; top >= 0; top -= 4) {
+      float va[4], vb[4];
+#pragma unroll
+      for (int u2 = 0; u2 < 4; ++u2) {
+        const int c = (top - u2) * 64 + lane - pad;
+        va[u2] = 0.f;
+        vb[u2] = 0.f;
+        if (top - u2 >= 0 && c >= J + 1 && c < wt) {
+          const float v0 = base[cat(r0, c, rs)];
+          va[u2] = v0 + base[cat(r1, c - J, rs)];
+          vb[u2] = v0 + base[cat(r1, c - J - 1, rs)];
+        }
+      }
+#pragma unroll
+      for (int u2 = 0; u2 < 4; ++u2) {
+        const int c = (top - u2) * 64 + lane - pad;
+        if (top - u2 >= 0 && c >= J + 1 && c < wt) {
+          base[cat(r0, c, rs)] = va[u2];
+          base[cat(r1, c, rs)] = vb[u2];
+        }
+      }
+    }
+  }
+}
+
+// Column-tile level with a compile-time block count (immediate LDS offsets, as above).  Block
+// bb >= 1 covers columns 64 bb - pad + lane, all of them >= J + 1; block 0 is masked.
+template <int NBLK>
+__device__ void cols_level_fast(float* S, int rs, int log2r, int ncls, int pad, int l) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
+  const int pairs = 1 << (log2r - 1);
+  const int units = ncls * pairs;
+  const int R = 1 << log2r;
+  for (int unit = wave; unit < units; unit += waves) {
+    const int cls = unit / pairs, pair = unit - cls * pairs;
+    const int ib = pair & ((1 << l) - 1), pp = pair >> l;
+    const int r0 = (pp << (l + 1)) | ib, r1 = r0 | (1 << l);
+    const int J = brev_bits(ib, l);
+    float* base = S + cls * R * rs;
+    const int cb1 = 64 - pad + lane;
+    const int c1 = cb1 - J, c2 = cb1 - J - 1;
+    float* a0 = base + r0 * rs + cb1 + (cb1 >> 5);
+    float* w1 = base + r1 * rs + cb1 + (cb1 >> 5);
+    const float* a1 = base + r1 * rs + c1 + (c1 >> 5);
+    const float* a2 = base + r1 * rs + c2 + (c2 >> 5);
+#pragma unroll
+    for (int top = NBLK - 1; top >= 1; top -= 4) {
+      float va[4], vb[4];
+#pragma unroll
+      for (int u2 = 0; u2 < 4; ++u2) {
+        const int k = top - u2;
+        if (k >= 1) {
+          const int off = 66 * (k - 1);
+          const float v0 = a0[off];
+          va[u2] = v0 + a1[off];
+          vb[u2] = v0 + a2[off];
+        }
+      }
+#pragma unroll
+      for (int u2 = 0; u2 < 4; ++u2) {
+        const int k = top - u2;
+        if (k >= 1) {
+          const int off = 66 * (k - 1);
+          a0[off] = va[u2];
+          w1[off] = vb[u2];
+        }
+      }
+    }
+    const int c = lane - pad;
+    if (c >= J + 1) {
+      const float v0 = base[cat(r0, c, rs)];
+      const float v1 = base[cat(r1, c - J, rs)];
+      const float v2 = base[cat(r1, c - J - 1, rs)];
+      base[cat(r0, c, rs)] = v0 + v1;
+      base[cat(r1, c, rs)] = v0 + v2;
+    }
+  }
+}
+
+template <int NCLS>
+__global__ void __launch_bounds__(512) fht_cols_kernel(PassArgs A) {
+  extern __shared__ float S[];
+  const int T = blockDim.x, tid = threadIdx.x;
+  const int N = 1 << A.log2n, mask = N - 1;
+  const int R = 1 << A.log2r;
+  const int F = A.levels;
+  const int W = 1 << A.log2w, H = A.halo, wt = W + H;
+  const int rs = (wt + (wt >> 5) + 1) | 1;
+  const int cblocks = N >> A.log2w;
+  const int cb = blockIdx.x % cblocks;
+  const int cx = cb << A.log2w;                 // first output column of the tile
+  if constexpr (NCLS == 2) {
+    const int strips = N >> A.log2r;
+    const int rest = blockIdx.x / cblocks;
+    const int j = rest % strips, b = rest / strips;
+    const int qa = (A.out_mode == OUT_IMG_V) ? 0 : 2;
+    const int row0 = j * R;
+    const float* c0 = A.in + ((size_t)b * 4 + qa) * N * N;
+    const float* c1 = c0 + (size_t)N * N;
+    cols_load(A, S, rs, c0, row0, (cx - H) & mask);
+    cols_load(A, S + R * rs, rs, c1, row0, (N - cx - W - H) & mask);
+    __syncthreads();
+    const int pad = 64 * ((wt + 63) >> 6) - wt;
+    for (int l = 0; l < F; ++l) {
+      if (((wt + 63) >> 6) == 5) cols_level_fast<5>(S, rs, A.log2r, 2, pad, l);
+      else cols_level(S, rs, A.log2r, 2, wt, l);
+      __syncthreads();
+    }
+    const float* s0 = S;
+    const float* s1 = S + R * rs;
+    float* img = A.out + (size_t)b * N * N;
+    if (A.out_mode == OUT_IMG_V) {
+      // image[j R + i][cx + u] = c0[i][cx + u] + c1[i][N - 1 - cx - u]
+      for (int e = tid; e < R * W; e += T) {
+        const int i = e >> A.log2w, u = e & (W - 1);
+        const int rho = brev_bits(i, F);
+        img[(size_t)(row0 + i) * N + cx + u] = s0[cat(rho, H + u, rs)] + s1[cat(rho, H + W - 1 - u, rs)];
+      }
+    } else {
+      // image[cx + u][j R + i] += c2[i][cx + u] + c3[i][N - 1 - cx - u]
+      for (int e = tid; e < R * W; e += T) {
+        const int i = e & (R - 1), u = e >> A.log2r;
+        const int rho = brev_bits(i, F);
+        float* p = img + (size_t)(cx + u) * N + row0 + i;
+        *p = *p + s0[cat(rho, H + u, rs)] + s1[cat(rho, H + W - 1 - u, rs)];
+      }
+    }
+  } else {
+    const int tiles = N >> A.log2r;
+    const int rest = blockIdx.x / cblocks;
+    const int tile = rest % tiles, bq = rest / tiles;
+    const int vbits = A.k_hi - F;
+    const int j = tile >> vbits, v = tile & ((1 << vbits) - 1);
+    const int row0 = (j << A.k_hi) + (v << F);
+    const int k_lo = A.k_hi - F;
+    const float* cls = A.in + (size_t)bq * N * N;
+    cols_load(A, S, rs, cls, row0, (cx - H) & mask);
+    __syncthreads();
+    const int pad = 64 * ((wt + 63) >> 6) - wt;
+    for (int l = 0; l < F; ++l) {
+      if (((wt + 63) >> 6) == 5) cols_level_fast<5>(S, rs, A.log2r, 1, pad, l);
+      else cols_level(S, rs, A.log2r, 1, wt, l);
+      __syncthreads();
+    }
+    float* dst = A.out + (size_t)bq * N * N;
+    for (int e = tid; e < R * W; e += T) {
+      const int rho = e >> A.log2w, u = e & (W - 1);
+      const int i = brev_bits(rho, F);
+      const int orow = (((j << F) + i) << k_lo) + v;
+      const int o = (v * i) & mask;
+      dst[(size_t)orow * N + ((cx + u + o) & mask)] = S[cat(rho, H + u, rs)];
+    }
+  }
+}
+
 template <typename Kern>
 hipError_t launch_kernel(Kern kern, const PassArgs& a, int blocks, int threads, size_t lds,
                          hipStream_t stream) {
@@ -494,6 +868,39 @@ hipError_t launch_lk(const PassArgs& a, int batch, hipStream_t stream) {
 }
 
 }  // namespace
+
+template <int L, int NBLK>
+hipError_t launch_first_ln(const PassArgs& a, int grid, hipStream_t stream) {
+  const int threads = (1 << a.log2r) << a.log2c;
+  const size_t lds = pass_lds_bytes(a);
+  switch (a.order) {
+    case 0: return launch_kernel(fht_first_kernel<L, 0, NBLK>, a, grid, threads, lds, stream);
+    case 1: return launch_kernel(fht_first_kernel<L, 1, NBLK>, a, grid, threads, lds, stream);
+    case 2: return launch_kernel(fht_first_kernel<L, 2, NBLK>, a, grid, threads, lds, stream);
+    case 3: return launch_kernel(fht_first_kernel<L, 3, NBLK>, a, grid, threads, lds, stream);
+    case 4: return launch_kernel(fht_first_kernel<L, 4, NBLK>, a, grid, threads, lds, stream);
+    case 8: return launch_kernel(fht_first_kernel<L, 8, NBLK>, a, grid, threads, lds, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// 64-column blocks per streaming unit of a pass: W / 64 with W = N / max(1, waves / pairs).
+inline int stream_blocks(const PassArgs& a) {
+  const int threads = (1 << a.log2r) << a.log2c;
+  const int waves = threads >> 6, pairs = 1 << (a.log2r - 1);
+  const int segs = waves > pairs ? waves / pairs : 1;
+  return ((1 << a.log2n) / segs) >> 6;
+}
+
+template <int L>
+hipError_t launch_first_l(const PassArgs& a, int grid, hipStream_t stream) {
+  switch (stream_blocks(a)) {
+    case 4: return launch_first_ln<L, 4>(a, grid, stream);
+    case 8: return launch_first_ln<L, 8>(a, grid, stream);
+    case 16: return launch_first_ln<L, 16>(a, grid, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 // Orders 5..7 run on the order-8 kernels with zero-padded coefficients (bit-identical: the
 // padded taps add exact zeros).

@@ -17,6 +17,7 @@ struct fbp_plan_s {
   uint32_t flags = 0;
   hipStream_t stream = nullptr;
   int device = 0;
+  int cus = 0;                // compute units of the device
   int log2l = 0, log2c = 0;   // chunk length and chunks per row of the filter
   int rs = 0;                 // LDS row stride
   std::vector<int> levels;    // levels per pass, first pass first
@@ -136,9 +137,16 @@ void clear_recs(fbp_plan_s* p) {
   p->recs.clear();
 }
 
+hipError_t dispatch(fbp_plan_s* p, const PassArgs& A, int batch, int family) {
+  if (family == PASS_COLS) return launch_cols(A, batch, p->stream);
+  if (family == PASS_FIRST) return launch_pass_kind(A, batch, PASS_FIRST, p->cus, p->stream);
+  return launch_pass(A, batch, p->stream);
+}
+
 // Launch one pass, bracketed by timing events when the plan is profiling.
-hipError_t timed_pass(fbp_plan_s* p, const PassArgs& A, int batch, int kind) {
-  if (!p->profiling) return launch_pass(A, batch, p->stream);
+hipError_t timed_pass(fbp_plan_s* p, const PassArgs& A, int batch, int kind,
+                      int family = PASS_ROWS) {
+  if (!p->profiling) return dispatch(p, A, batch, family);
   fbp_plan_s::Rec r;
   r.kind = kind;
   if (hipEventCreate(&r.start) != hipSuccess) return hipErrorOutOfMemory;
@@ -147,7 +155,7 @@ hipError_t timed_pass(fbp_plan_s* p, const PassArgs& A, int batch, int kind) {
     return hipErrorOutOfMemory;
   }
   hipEventRecord(r.start, p->stream);
-  hipError_t e = launch_pass(A, batch, p->stream);
+  hipError_t e = dispatch(p, A, batch, family);
   hipEventRecord(r.stop, p->stream);
   p->recs.push_back(r);
   return e;
@@ -206,23 +214,37 @@ int run_passes(fbp_plan_s* p, const float* in, float* out, int batch, bool forwa
     A.order = (first && filter) ? kernel_order(p->order) : 0;
     hipError_t e;
     const int kind = forward ? FBP_KERNEL_FORWARD : (first ? FBP_KERNEL_FIRST : FBP_KERNEL_MIDDLE);
+    // column tiles for the middle and last back-projection passes (they carry no filter)
+    const bool cols = !forward && !first && p->log2n >= 8;
+    if (cols) {
+      A.log2w = std::min(8, p->log2n);
+      A.halo = std::max(4, 1 << F);
+    }
     if (!last) {
       float* dst = p->d_scratch[pi & 1];
       A.out = dst;
       A.out_mode = OUT_ROWS;
-      e = timed_pass(p, A, batch, kind);
+      if (cols) {
+        e = timed_pass(p, A, batch, kind, PASS_COLS);
+      } else if (first && !forward && p->log2l == 5 && pass_streams(A) &&
+                 first_pass_supported(A)) {
+        A.total_tiles = batch * 4 * (p->n >> F);
+        e = timed_pass(p, A, batch, kind, PASS_FIRST);
+      } else {
+        e = timed_pass(p, A, batch, kind, PASS_ROWS);
+      }
       src = dst;
     } else if (forward) {
       A.out = out;
       A.out_mode = OUT_LINO_MIRROR;
-      e = timed_pass(p, A, batch, kind);
+      e = timed_pass(p, A, batch, kind, PASS_ROWS);
     } else {
       A.out = out;
       A.out_mode = OUT_IMG_V;
-      e = timed_pass(p, A, batch, FBP_KERNEL_LAST_V);
+      e = timed_pass(p, A, batch, FBP_KERNEL_LAST_V, cols ? PASS_COLS : PASS_ROWS);
       if (e == hipSuccess) {
         A.out_mode = OUT_IMG_H;
-        e = timed_pass(p, A, batch, FBP_KERNEL_LAST_H);
+        e = timed_pass(p, A, batch, FBP_KERNEL_LAST_H, cols ? PASS_COLS : PASS_ROWS);
       }
     }
     if (e != hipSuccess) return FBP_EDEVICE;
@@ -234,6 +256,28 @@ int run_passes(fbp_plan_s* p, const float* in, float* out, int batch, bool forwa
 }  // namespace
 
 namespace fhtfbp {
+// The persistent first pass is instantiated for 4, 8 or 16 column blocks per streaming unit.
+bool first_pass_supported(const PassArgs& a) {
+  const int threads = (1 << a.log2r) << a.log2c;
+  const int waves = threads >> 6, pairs = 1 << (a.log2r - 1);
+  const int segs = waves > pairs ? waves / pairs : 1;
+  const int nblk = ((1 << a.log2n) / segs) >> 6;
+  return nblk == 4 || nblk == 8 || nblk == 16;
+}
+
+// Persistent passes: one block per compute unit times the blocks a unit holds at once.
+hipError_t launch_pass_kind(const PassArgs& a, int batch, int kind, int cus, hipStream_t stream) {
+  (void)batch;
+  (void)kind;
+  if (a.log2l != 5) return hipErrorInvalidValue;
+  const int threads = (1 << a.log2r) << a.log2c;
+  const size_t lds = pass_lds_bytes(a);
+  int per_cu = (int)(kLdsBudget / std::max<size_t>(lds, 1));
+  per_cu = std::max(1, std::min(per_cu, 2048 / threads));
+  const int grid = std::min(a.total_tiles, cus * per_cu);
+  return launch_first_l<32>(a, grid, stream);
+}
+
 hipError_t launch_pass(const PassArgs& a, int batch, hipStream_t stream) {
   switch (a.log2l) {
     case 2: return launch_pass_l<4>(a, batch, stream);
@@ -287,7 +331,9 @@ int fbp_plan(const fbp_plan_desc* d, fbp_plan_t* out) {
   p->stream = (hipStream_t)d->stream;
   p->b.assign(d->b, d->b + (size_t)G * K);
   p->a.assign(d->a, d->a + (size_t)G * K);
-  if (hipGetDevice(&p->device) != hipSuccess) {
+  if (hipGetDevice(&p->device) != hipSuccess ||
+      hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, p->device) !=
+          hipSuccess) {
     delete p;
     return FBP_EDEVICE;
   }

@@ -43,7 +43,10 @@ struct PassArgs {
   const float* scale;  // [N] row factor c_t
   const int* sigma;    // [N] window start of row t
   int rs;              // LDS row stride in floats
-  int log2l;           // chunk length L = 2^log2l
+  int log2l;           // chunk length L = 2^log2l (also the skew period of the LDS rows)
+  int log2w;           // column-tiled passes: output columns per tile = 2^log2w
+  int halo;            // column-tiled passes: extra columns loaded below the tile (>= 2^F - 1)
+  int total_tiles;     // persistent passes: tiles over the whole batch
 };
 
 // Launch one pass over `batch` slices on `stream`.  Returns hipSuccess or the launch error.
@@ -69,6 +72,31 @@ inline size_t pass_lds_bytes(const PassArgs& a) {
   const int waves = threads >> 6, pairs = 1 << (a.log2r - 1);
   return tile + (size_t)(waves > pairs ? waves : pairs) * 64 * sizeof(float);
 }
+
+// Kernel families a pass can run on.
+enum PassKind : int {
+  PASS_ROWS = 0,        // full-row tiles, one per block (any mode)
+  PASS_FIRST = 1,       // full-row tiles, persistent blocks with the next tile prefetched
+  PASS_COLS = 2,        // column tiles with a halo (no filter): OUT_ROWS, OUT_IMG_V, OUT_IMG_H
+};
+hipError_t launch_pass_kind(const PassArgs& a, int batch, int kind, int grid, hipStream_t stream);
+template <int L>
+hipError_t launch_first_l(const PassArgs& a, int grid, hipStream_t stream);
+hipError_t launch_cols(const PassArgs& a, int batch, hipStream_t stream);
+bool first_pass_supported(const PassArgs& a);
+
+// LDS bytes and threads of a column-tiled pass.
+inline int cols_rs(const PassArgs& a) {
+  const int wt = (1 << a.log2w) + a.halo;
+  return (wt + (wt >> 5) + 1) | 1;
+}
+inline int cols_classes(const PassArgs& a) {
+  return (a.out_mode == OUT_IMG_V || a.out_mode == OUT_IMG_H) ? 2 : 1;
+}
+inline size_t cols_lds_bytes(const PassArgs& a) {
+  return (size_t)cols_classes(a) * (1 << a.log2r) * cols_rs(a) * sizeof(float);
+}
+inline int cols_threads(const PassArgs& a) { return cols_classes(a) == 2 ? 512 : 256; }
 
 // Direct FBP comparator kernels.
 hipError_t launch_direct_filter(const float* sino, float* work, int rows, int n_det,

@@ -100,6 +100,15 @@ int fht_forward(fbp_plan_t plan, const float* img, float* lino, int32_t batch);
  * first back-projection pass (the linogram is read once).  `lino` is not modified. */
 int fbp_reconstruct(fbp_plan_t plan, const float* lino, float* img, int32_t batch);
 
+/* Gradient of a loss with respect to the recursive-filter coefficients, for learning them:
+ * `lino` is the filter input and `grad_out` dL/d(fbp_filter output), both [batch][4][N][N].
+ * Writes grad [groups][2][order] (device, float64): dL/db_k then dL/da_k per group, summed over
+ * the batch and the group's rows in a fixed order (deterministic).  Adjoint-state form: the
+ * gradient of a recursion is an opposite-direction recursion of the output gradient, run in
+ * the same chunked scan as the filter.  N <= 2048. */
+int fbp_filter_coef_grad(fbp_plan_t plan, const float* lino, const float* grad_out,
+                         double* grad, int32_t batch);
+
 /* Host-side fit of the recursive ramp pair (Sec. 3): minimise the squared error between the
  * impulse response of eq 9 and the causal half h+ of eq 10 over n = 0..length-1 by the
  * Nelder-Mead simplex method (a parameterised through reflection coefficients, so the fit is
@@ -117,6 +126,15 @@ int fbp_fit_ramp_iir(int32_t order, int32_t length, uint32_t flags, double* b, d
  * interpolation into img [batch][n][n].  Theta(n_angles n^2) per slice. */
 int fbp_direct_parallel(const float* sino, float* work, float* img, int32_t batch, int32_t n,
                         int32_t n_angles, int32_t n_det, void* stream);
+
+/* Direct FBP on the linogram itself (Sec. 2-3: the exact ramp of eq 7-8 in place of the
+ * recursive pair, exact line positions in place of dyadic patterns): every row (q, t) is read
+ * over the same window as fbp_filter, filtered by the full-length FIR, scaled by c_t into
+ * `work` ([batch][4N][N] floats, window order), and back-projected with linear interpolation at
+ * the exact intercept of each pixel's line; the four classes are summed.  The accuracy judge
+ * of the method (and the training target of the learned filter).  Theta(N^3) per slice. */
+int fbp_direct_linogram(const float* lino, float* work, float* img, int32_t batch, int32_t n,
+                        void* stream);
 
 /* The two halves of fbp_direct_parallel, for timing them apart. */
 int fbp_direct_filter(const float* sino, float* work, int32_t batch, int32_t n_angles,
@@ -142,6 +160,40 @@ int fbp_plan_profile(fbp_plan_t plan, int32_t enable);
 /* Synchronise the recorded events, write per-kind total milliseconds and launch counts
  * (arrays of FBP_KERNEL_KINDS entries) and clear the record. */
 int fbp_plan_profile_read(fbp_plan_t plan, double* total_ms, int32_t* launches);
+
+/* ---- learned residual correction ------------------------------------------------------ */
+/* A small residual network after the reconstruction, out = img + conv3(relu(conv2(relu(conv1(
+ * img))))), 3x3 convolutions with zero padding, 16 hidden channels: the learned part that
+ * corrects what the low-order recursive filter leaves.  Convolutions run on the matrix cores
+ * with BF16 operands and FP32 accumulation.  Images with one channel are FP32 [b][y][x];
+ * 16-channel activations are BF16 NHWC [b][y][x][16] (uint16_t storage).  Supported
+ * (cin, cout): (1, 16), (16, 16), (16, 1). */
+
+/* Pack FP32 weights w[cout][cin][3][3] into the matrix-core operand order (fbp_cnn_packed_elems
+ * (cin) BF16 values; for transpose_flip, fbp_cnn_packed_elems(cout)).  transpose_flip packs the
+ * weights of the convolution that gives the gradient with respect to the input (channels
+ * swapped, taps mirrored). */
+int fbp_cnn_pack(const float* w, uint16_t* packed, int32_t cin, int32_t cout,
+                 int32_t transpose_flip, void* stream);
+int32_t fbp_cnn_packed_elems(int32_t cin);
+
+/* One convolution: cout == 16 writes out16 = relu?(conv + bias) times (mask > 0) when mask is
+ * given (the ReLU derivative of the layer below, for the backward pass); cout == 1 writes
+ * out32 = conv + bias + resid (resid optional).  bias may be NULL.  w must be a multiple of 16. */
+int fbp_cnn_conv(int32_t cin, int32_t cout, const float* in32, const uint16_t* in16,
+                 const uint16_t* wpacked, const float* bias, const uint16_t* mask,
+                 const float* resid, uint16_t* out16, float* out32, int32_t relu, int32_t batch,
+                 int32_t h, int32_t w, void* stream);
+
+/* Weight and bias gradients, out[cout * cin * 9 + cout] (FP32): dw[co][ci][tap] =
+ * sum_p dz[p][co] in[p + off(tap)][ci], db[co] = sum_p dz[p][co]; dz has cout channels and in
+ * cin.  `partial` is caller-owned scratch of fbp_cnn_wgrad_partial_floats floats; the block
+ * sums are added in a fixed order (deterministic).  w must be a multiple of 64. */
+int64_t fbp_cnn_wgrad_partial_floats(int32_t cin, int32_t cout, int32_t batch, int32_t h,
+                                     int32_t w);
+int fbp_cnn_wgrad(int32_t cin, int32_t cout, const float* dz32, const uint16_t* dz16,
+                  const float* in32, const uint16_t* in16, float* partial, float* out,
+                  int32_t batch, int32_t h, int32_t w, void* stream);
 
 /* Human-readable text of an error code (static storage). */
 const char* fbp_strerror(int code);

@@ -439,16 +439,30 @@ def relative_rmse(a: torch.Tensor, b: torch.Tensor, mask: torch.Tensor | None = 
 # Learned residual correction applied after the reconstruction
 # ---------------------------------------------------------------------------------------------
 
-def residual_cnn(img: torch.Tensor, weights: list[torch.Tensor], biases: list[torch.Tensor]):
+def _round_bf16(x: torch.Tensor) -> torch.Tensor:
+    """Round to the nearest bfloat16 value (ties to even), returned in float64."""
+    return x.to(torch.float32).to(torch.bfloat16).to(DT)
+
+
+def residual_cnn(img: torch.Tensor, weights: list[torch.Tensor], biases: list[torch.Tensor], *,
+                 bf16_storage: bool = False):
     """out = img + conv3(relu(conv2(relu(conv1(img))))), 3x3 convolutions, zero padding 1.
 
     ``img`` is [B, N, N]; weights[l] is [C_out, C_in, 3, 3].  Plain conv2d as the library step.
+    With ``bf16_storage`` the convolution inputs, the weights and the hidden activations are
+    rounded to bfloat16 (the storage format of the matrix-core network); arithmetic stays float64
+    and the skip connection uses the unrounded image.
     """
     x = img.to(DT)[:, None]
-    h = x
+    h = _round_bf16(x) if bf16_storage else x
     L = len(weights)
     for layer in range(L):
-        h = torch.nn.functional.conv2d(h, weights[layer].to(DT), biases[layer].to(DT), padding=1)
+        w = weights[layer].to(DT)
+        if bf16_storage:
+            w = _round_bf16(w)
+        h = torch.nn.functional.conv2d(h, w, biases[layer].to(DT), padding=1)
         if layer < L - 1:
             h = torch.relu(h)
+            if bf16_storage:
+                h = _round_bf16(h)
     return (x + h)[:, 0]

@@ -7,5 +7,6 @@ from .api import (  # noqa: F401
     FBP_NO_ROW_SCALE, FBP_INPUT_IS_FHT, FBP_ZERO_WINDOW, FbpError, Plan,
     fbp_plan, fbp_plan_set_coefficients, fbp_filter, fht_backproject, fht_forward,
     fbp_reconstruct, fbp_fit_ramp_iir, fbp_direct_parallel, fbp_direct_filter,
-    fbp_direct_backproject, load_library, strerror,
+    fbp_direct_backproject, fbp_direct_linogram, fbp_filter_coef_grad, load_library, strerror,
 )
+from .autograd import FBPReconstruct, fbp_reconstruct_autograd  # noqa: F401,E402

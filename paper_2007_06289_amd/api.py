@@ -82,6 +82,14 @@ def load_library():
         "fbp_fit_ramp_iir": ([i32, i32, u32, dp, dp, dp], ctypes.c_int),
         "fbp_direct_parallel": ([vp, vp, vp, i32, i32, i32, i32, vp], ctypes.c_int),
         "fbp_direct_filter": ([vp, vp, i32, i32, i32, vp], ctypes.c_int),
+        "fbp_direct_linogram": ([vp, vp, vp, i32, i32, vp], ctypes.c_int),
+        "fbp_filter_coef_grad": ([vp, vp, vp, vp, i32], ctypes.c_int),
+        "fbp_cnn_pack": ([vp, vp, i32, i32, i32, vp], ctypes.c_int),
+        "fbp_cnn_packed_elems": ([i32], ctypes.c_int32),
+        "fbp_cnn_conv": ([i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, i32, i32, i32, i32, vp],
+                         ctypes.c_int),
+        "fbp_cnn_wgrad_partial_floats": ([i32, i32, i32, i32, i32], ctypes.c_int64),
+        "fbp_cnn_wgrad": ([i32, i32, vp, vp, vp, vp, vp, vp, i32, i32, i32, vp], ctypes.c_int),
         "fbp_direct_backproject": ([vp, vp, i32, i32, i32, i32, vp], ctypes.c_int),
         "fbp_strerror": ([ctypes.c_int], ctypes.c_char_p),
         "fbp_plan_profile": ([vp, i32], ctypes.c_int),
@@ -274,6 +282,22 @@ def fbp_reconstruct(plan: Plan, lino: torch.Tensor, img: torch.Tensor | None = N
     return img
 
 
+def fbp_filter_coef_grad(plan: Plan, lino: torch.Tensor, grad_out: torch.Tensor) -> torch.Tensor:
+    """dL/d(b, a) per coefficient group, [groups, 2, order] float64 on the GPU, given the filter
+    input and the gradient with respect to the filter output."""
+    B = _batch_of(lino, 3, "lino")
+    shape = (B, 4, plan.n, plan.n)
+    out = torch.empty((plan.groups, 2, plan.order), device=lino.device, dtype=torch.float64)
+    if not out.is_contiguous():
+        raise ValueError("internal: output not contiguous")
+    plan.bind_stream()
+    _check(load_library().fbp_filter_coef_grad(plan.handle, _dev_ptr(lino, "lino", shape),
+                                               _dev_ptr(grad_out, "grad_out", shape),
+                                               ctypes.c_void_p(out.data_ptr()), B),
+           "fbp_filter_coef_grad")
+    return out
+
+
 def fbp_fit_ramp_iir(order: int, length: int, dc_zero: bool = True):
     """Fit the recursive ramp pair on the host; returns (b, a, relative L2 error)."""
     b = np.zeros(order, dtype=np.float64)
@@ -302,6 +326,21 @@ def fbp_direct_parallel(sino: torch.Tensor, n: int, img: torch.Tensor | None = N
     return img
 
 
+def fbp_direct_linogram(lino: torch.Tensor, img: torch.Tensor | None = None,
+                        work: torch.Tensor | None = None):
+    """Direct FBP (exact ramp, exact line positions) of a linogram [B,4,N,N] -> [B,N,N]."""
+    B, N = _batch_of(lino, 3, "lino"), lino.shape[-1]
+    if img is None:
+        img = torch.empty((B, N, N), device=lino.device, dtype=torch.float32)
+    if work is None:
+        work = torch.empty((B, 4 * N, N), device=lino.device, dtype=torch.float32)
+    _check(load_library().fbp_direct_linogram(_dev_ptr(lino, "lino", (B, 4, N, N)),
+                                              _dev_ptr(work, "work", (B, 4 * N, N)),
+                                              _dev_ptr(img, "img", (B, N, N)), B, int(N),
+                                              _stream_ptr()), "fbp_direct_linogram")
+    return img
+
+
 def fbp_direct_filter(sino: torch.Tensor, work: torch.Tensor):
     B, P, Nd = _batch_of(sino, 2, "sino"), sino.shape[1], sino.shape[2]
     _check(load_library().fbp_direct_filter(_dev_ptr(sino, "sino"),
@@ -317,3 +356,72 @@ def fbp_direct_backproject(work: torch.Tensor, n: int, img: torch.Tensor):
                                                  int(P), int(Nd), _stream_ptr()),
            "fbp_direct_backproject")
     return img
+
+
+# ---- learned residual correction (3x3 convolutions on the matrix cores) ------------------------
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _check_dev(t, name, dtype, shape=None):
+    if t is None:
+        return
+    if t.device.type != "cuda" or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor on the GPU")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+def fbp_cnn_pack(w: torch.Tensor, transpose_flip: bool = False) -> torch.Tensor:
+    """Pack FP32 weights [cout, cin, 3, 3] into the BF16 matrix-core operand order (int16)."""
+    cout, cin = int(w.shape[0]), int(w.shape[1])
+    _check_dev(w, "w", torch.float32, (cout, cin, 3, 3))
+    lib = load_library()
+    n = lib.fbp_cnn_packed_elems(cout if transpose_flip else cin)
+    out = torch.empty(n, device=w.device, dtype=torch.int16)
+    _check(lib.fbp_cnn_pack(_ptr(w), _ptr(out), cin, cout, 1 if transpose_flip else 0,
+                            _stream_ptr()), "fbp_cnn_pack")
+    return out
+
+
+def fbp_cnn_conv(cin: int, cout: int, x: torch.Tensor, wpacked: torch.Tensor,
+                 bias: torch.Tensor | None = None, mask: torch.Tensor | None = None,
+                 resid: torch.Tensor | None = None, relu: bool = False) -> torch.Tensor:
+    """One 3x3 convolution: x is FP32 [B,H,W] (cin 1) or BF16-as-int16 [B,H,W,16] (cin 16);
+    returns BF16-as-int16 [B,H,W,16] (cout 16) or FP32 [B,H,W] (cout 1)."""
+    B, H, W = int(x.shape[0]), int(x.shape[1]), int(x.shape[2])
+    if cin == 1:
+        _check_dev(x, "x", torch.float32, (B, H, W))
+    else:
+        _check_dev(x, "x", torch.int16, (B, H, W, 16))
+    _check_dev(mask, "mask", torch.int16, (B, H, W, 16))
+    _check_dev(resid, "resid", torch.float32, (B, H, W))
+    _check_dev(bias, "bias", torch.float32, (cout,))
+    if cout == 16:
+        out = torch.empty((B, H, W, 16), device=x.device, dtype=torch.int16)
+        o16, o32 = out, None
+    else:
+        out = torch.empty((B, H, W), device=x.device, dtype=torch.float32)
+        o16, o32 = None, out
+    _check(load_library().fbp_cnn_conv(cin, cout, _ptr(x) if cin == 1 else None,
+                                       _ptr(x) if cin == 16 else None, _ptr(wpacked), _ptr(bias),
+                                       _ptr(mask), _ptr(resid), _ptr(o16), _ptr(o32),
+                                       1 if relu else 0, B, H, W, _stream_ptr()), "fbp_cnn_conv")
+    return out
+
+
+def fbp_cnn_wgrad(cin: int, cout: int, dz: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
+    """[cout*cin*9 + cout] FP32: weight gradients then bias gradients."""
+    B, H, W = int(dz.shape[0]), int(dz.shape[1]), int(dz.shape[2])
+    lib = load_library()
+    nparts = lib.fbp_cnn_wgrad_partial_floats(cin, cout, B, H, W)
+    if nparts < 0:
+        raise FbpError(int(nparts), "fbp_cnn_wgrad_partial_floats")
+    partial = torch.empty(int(nparts), device=dz.device, dtype=torch.float32)
+    out = torch.empty(cout * cin * 9 + cout, device=dz.device, dtype=torch.float32)
+    _check(lib.fbp_cnn_wgrad(cin, cout, _ptr(dz) if cout == 1 else None,
+                             _ptr(dz) if cout == 16 else None, _ptr(x) if cin == 1 else None,
+                             _ptr(x) if cin == 16 else None, _ptr(partial), _ptr(out), B, H, W,
+                             _stream_ptr()), "fbp_cnn_wgrad")
+    return out

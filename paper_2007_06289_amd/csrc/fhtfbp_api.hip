@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -28,6 +29,8 @@ struct fbp_plan_s {
   int* d_sigma = nullptr;
   float* d_scratch[2] = {nullptr, nullptr};
   size_t scratch_floats = 0;
+  double* d_partial = nullptr;   // per-block sums of the coefficient gradient
+  size_t partial_doubles = 0;
   // kernel timing: event pairs recorded around launches while profiling is on
   bool profiling = false;
   struct Rec {
@@ -164,6 +167,7 @@ hipError_t timed_pass(fbp_plan_s* p, const PassArgs& A, int batch, int kind,
 void free_plan(fbp_plan_s* p) {
   if (!p) return;
   clear_recs(p);
+  hipFree(p->d_partial);
   hipFree(p->d_coef);
   hipFree(p->d_scale);
   hipFree(p->d_sigma);
@@ -289,6 +293,80 @@ hipError_t launch_pass(const PassArgs& a, int batch, hipStream_t stream) {
   }
 }
 }  // namespace fhtfbp
+
+namespace {
+
+// Per-row tables of the direct FBPs, built once per (geometry, sizes, device) and kept in device
+// memory for the life of the process.
+struct DirectTables {
+  int kind, n, rows, ndet, device;
+  float* aff = nullptr;   // [rows] float4: pos = X x + Y y + z
+  int* start = nullptr;   // [rows] window start (linogram only)
+  float* w = nullptr;     // [rows] row weight (linogram only)
+};
+std::mutex g_tables_mu;
+std::vector<DirectTables> g_tables;
+
+const DirectTables* direct_tables(int kind, int n, int rows, int ndet) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lock(g_tables_mu);
+  for (auto& t : g_tables)
+    if (t.kind == kind && t.n == n && t.rows == rows && t.ndet == ndet && t.device == dev)
+      return &t;
+  DirectTables t{kind, n, rows, ndet, dev};
+  std::vector<float> aff((size_t)rows * 4, 0.f), w(rows, 0.f);
+  std::vector<int> start(rows, 0);
+  const double pi = 3.14159265358979323846;
+  if (kind == 0) {   // uniform parallel beam: rows are angles i pi / rows
+    for (int a = 0; a < rows; ++a) {
+      aff[4 * a + 0] = (float)cos(pi * a / rows);
+      aff[4 * a + 1] = (float)sin(pi * a / rows);
+      aff[4 * a + 2] = (float)(0.5 * ndet - 0.5);
+    }
+  } else {           // linogram: row (q, t) over its window, pixel -> window position
+    const int N = n;
+    std::vector<double> th(N);
+    for (int tt = 0; tt < N; ++tt) th[tt] = atan((double)tt / (N - 1));
+    for (int q = 0; q < 4; ++q)
+      for (int tt = 0; tt < N; ++tt) {
+        const int r = q * N + tt;
+        const double m = (double)tt / (N - 1);
+        const int su = (N - 1 - tt) / 2 - N / 2;               // unwrapped window start
+        const double g = (0.5 * N - 0.5) * (1.0 - m) - su;
+        double al, be;
+        if (q == 0) { al = 1; be = -m; }
+        else if (q == 1) { al = -1; be = -m; }
+        else if (q == 2) { al = -m; be = 1; }
+        else { al = -m; be = -1; }
+        aff[4 * r + 0] = (float)al;
+        aff[4 * r + 1] = (float)be;
+        aff[4 * r + 2] = (float)g;
+        start[r] = ((su % N) + N) % N;
+        double wt;
+        if (tt == 0) wt = 0.5 * (th[1] - th[0]);
+        else if (tt == N - 1) wt = 0.5 * (th[N - 1] - th[N - 2]);
+        else wt = 0.5 * (th[tt + 1] - th[tt - 1]);
+        w[r] = (float)(sqrt(1.0 + m * m) * wt);
+      }
+  }
+  if (hipMalloc(&t.aff, aff.size() * sizeof(float)) != hipSuccess ||
+      hipMalloc(&t.start, rows * sizeof(int)) != hipSuccess ||
+      hipMalloc(&t.w, rows * sizeof(float)) != hipSuccess ||
+      hipMemcpy(t.aff, aff.data(), aff.size() * sizeof(float), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(t.start, start.data(), rows * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(t.w, w.data(), rows * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+    hipFree(t.aff);
+    hipFree(t.start);
+    hipFree(t.w);
+    return nullptr;
+  }
+  g_tables.push_back(t);
+  return &g_tables.back();
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -529,8 +607,8 @@ int fbp_direct_filter(const float* sino, float* work, int32_t batch, int32_t n_a
   if (batch == 0) return FBP_OK;
   if (!sino || !work) return FBP_EINVAL;
   const float w = (float)(3.14159265358979323846 / n_angles);
-  return launch_direct_filter(sino, work, batch * n_angles, n_det, w, (hipStream_t)stream) ==
-                 hipSuccess
+  return launch_direct_filter(sino, work, batch * n_angles, n_det, w, nullptr, nullptr, 1,
+                              (hipStream_t)stream) == hipSuccess
              ? FBP_OK
              : FBP_EDEVICE;
 }
@@ -541,8 +619,10 @@ int fbp_direct_backproject(const float* work, float* img, int32_t batch, int32_t
     return FBP_EINVAL;
   if (batch == 0) return FBP_OK;
   if (!work || !img) return FBP_EINVAL;
-  return launch_direct_backproject(work, img, batch, n, n_angles, n_det, (hipStream_t)stream) ==
-                 hipSuccess
+  const DirectTables* t = direct_tables(0, n, n_angles, n_det);
+  if (!t) return FBP_ENOMEM;
+  return launch_direct_backproject(work, img, batch, n, n_angles, n_det, t->aff,
+                                   (hipStream_t)stream) == hipSuccess
              ? FBP_OK
              : FBP_EDEVICE;
 }
@@ -557,6 +637,114 @@ int fbp_direct_parallel(const float* sino, float* work, float* img, int32_t batc
   int rc = fbp_direct_filter(sino, work, batch, n_angles, n_det, stream);
   if (rc != FBP_OK) return rc;
   return fbp_direct_backproject(work, img, batch, n, n_angles, n_det, stream);
+}
+
+int fbp_filter_coef_grad(fbp_plan_t p, const float* lino, const float* grad_out, double* grad,
+                         int32_t batch) {
+  int rc = check_batch(p, batch);
+  if (rc != FBP_OK) return rc;
+  if (!lino || !grad_out || !grad) return FBP_EINVAL;
+  if (p->log2l > 5) return FBP_ERANGE;   // 64-sample chunks (N = 4096) are not supported here
+  PassArgs A = base_args(p);
+  A.in = lino;
+  A.order = kernel_order(p->order);
+  // rows per block: <= 512 threads, two tiles of rows in LDS, inside one coefficient group
+  int log2r = std::min(p->log2n, 9 - p->log2c);
+  while (log2r > 0 && (size_t)2 * (1 << log2r) * p->rs * 4 > (size_t)kLdsBudget) --log2r;
+  while (log2r > 0 && ((4 * p->n / p->groups) % (1 << log2r)) != 0) --log2r;
+  A.log2r = log2r;
+  const int K = A.order;
+  const size_t blocks = (size_t)std::max(batch, 1) * 4 * (p->n >> log2r);
+  const size_t need = blocks * 2 * K;
+  if (need > p->partial_doubles) {
+    hipStreamSynchronize(p->stream);
+    hipFree(p->d_partial);
+    p->d_partial = nullptr;
+    p->partial_doubles = 0;
+    if (hipMalloc(&p->d_partial, need * sizeof(double)) != hipSuccess) return FBP_ENOMEM;
+    p->partial_doubles = need;
+  }
+  if (batch == 0) {
+    std::vector<double> zeros((size_t)p->groups * 2 * p->order, 0.0);
+    return hipMemcpyAsync(grad, zeros.data(), zeros.size() * sizeof(double),
+                          hipMemcpyHostToDevice, p->stream) == hipSuccess &&
+                   hipStreamSynchronize(p->stream) == hipSuccess
+               ? FBP_OK
+               : FBP_EDEVICE;
+  }
+  return launch_coef_grad(A, grad_out, p->d_partial, grad, batch, p->order, p->stream) ==
+                 hipSuccess
+             ? FBP_OK
+             : FBP_EDEVICE;
+}
+
+namespace {
+bool cnn_shape_ok(int cin, int cout) {
+  return (cin == 1 && cout == 16) || (cin == 16 && cout == 16) || (cin == 16 && cout == 1);
+}
+}  // namespace
+
+int fbp_cnn_pack(const float* w, uint16_t* packed, int32_t cin, int32_t cout,
+                 int32_t transpose_flip, void* stream) {
+  if (!w || !packed || !(cnn_shape_ok(cin, cout) || (cin == 1 && cout == 1))) return FBP_EINVAL;
+  return launch_cnn_pack(w, packed, cin, cout, transpose_flip ? 1 : 0, (hipStream_t)stream) ==
+                 hipSuccess
+             ? FBP_OK
+             : FBP_EDEVICE;
+}
+
+int32_t fbp_cnn_packed_elems(int32_t cin) { return cin == 16 ? 5 * 64 * 8 : 64 * 8; }
+
+int fbp_cnn_conv(int32_t cin, int32_t cout, const float* in32, const uint16_t* in16,
+                 const uint16_t* wpacked, const float* bias, const uint16_t* mask,
+                 const float* resid, uint16_t* out16, float* out32, int32_t relu, int32_t batch,
+                 int32_t h, int32_t w, void* stream) {
+  if (!cnn_shape_ok(cin, cout) || batch < 0 || h < 1 || w < 16 || (w % 16) != 0) return FBP_EINVAL;
+  if (batch == 0) return FBP_OK;
+  if (!wpacked || (cin == 1 && !in32) || (cin == 16 && !in16) || (cout == 16 && !out16) ||
+      (cout == 1 && !out32) || (mask && cout != 16))
+    return FBP_EINVAL;
+  return launch_cnn_conv(cin, cout, in32, in16, wpacked, bias, mask, resid, out16, out32,
+                         relu ? 1 : 0, batch, h, w, (hipStream_t)stream) == hipSuccess
+             ? FBP_OK
+             : FBP_EDEVICE;
+}
+
+int64_t fbp_cnn_wgrad_partial_floats(int32_t cin, int32_t cout, int32_t batch, int32_t h,
+                                     int32_t w) {
+  if (!cnn_shape_ok(cin, cout) || batch < 1 || h < 1 || w < 64 || (w % 64) != 0) return FBP_EINVAL;
+  const int64_t rows = cnn_wgrad_rows();
+  const int64_t blocks = (int64_t)batch * (w / 64) * ((h + rows - 1) / rows);
+  return blocks * (cout * cin * 9 + cout);
+}
+
+int fbp_cnn_wgrad(int32_t cin, int32_t cout, const float* dz32, const uint16_t* dz16,
+                  const float* in32, const uint16_t* in16, float* partial, float* out,
+                  int32_t batch, int32_t h, int32_t w, void* stream) {
+  if (!cnn_shape_ok(cin, cout) || batch < 1 || h < 1 || w < 64 || (w % 64) != 0) return FBP_EINVAL;
+  if (!partial || !out || (cout == 1 && !dz32) || (cout == 16 && !dz16) || (cin == 1 && !in32) ||
+      (cin == 16 && !in16))
+    return FBP_EINVAL;
+  return launch_cnn_wgrad(cin, cout, dz32, dz16, in32, in16, partial, out, batch, h, w,
+                          (hipStream_t)stream) == hipSuccess
+             ? FBP_OK
+             : FBP_EDEVICE;
+}
+
+int fbp_direct_linogram(const float* lino, float* work, float* img, int32_t batch, int32_t n,
+                        void* stream) {
+  if (batch < 0 || n < 32 || !is_pow2(n) || n > 4096) return FBP_EINVAL;
+  if (batch == 0) return FBP_OK;
+  if (!lino || !work || !img) return FBP_EINVAL;
+  const DirectTables* t = direct_tables(1, n, 4 * n, n);
+  if (!t) return FBP_ENOMEM;
+  hipStream_t s = (hipStream_t)stream;
+  if (launch_direct_filter(lino, work, batch * 4 * n, n, 1.f, t->start, t->w, 4 * n, s) !=
+      hipSuccess)
+    return FBP_EDEVICE;
+  return launch_direct_backproject(work, img, batch, n, 4 * n, n, t->aff, s) == hipSuccess
+             ? FBP_OK
+             : FBP_EDEVICE;
 }
 
 }  // extern "C"

@@ -98,10 +98,28 @@ inline size_t cols_lds_bytes(const PassArgs& a) {
 }
 inline int cols_threads(const PassArgs& a) { return cols_classes(a) == 2 ? 512 : 256; }
 
+// Coefficient gradient of the recursive pair (writes out[groups][2][K0]).
+hipError_t launch_coef_grad(const PassArgs& a, const float* g, double* partial, double* out,
+                            int batch, int K0, hipStream_t stream);
+
+// Learned residual correction (3x3 convolutions, BF16 matrix cores).
+hipError_t launch_cnn_pack(const float* w, uint16_t* packed, int cin, int cout, int transpose_flip,
+                           hipStream_t stream);
+hipError_t launch_cnn_conv(int cin, int cout, const float* in32, const uint16_t* in16,
+                           const uint16_t* wop, const float* bias, const uint16_t* mask,
+                           const float* resid, uint16_t* out16, float* out32, int relu, int batch,
+                           int H, int W, hipStream_t stream);
+hipError_t launch_cnn_wgrad(int cin, int cout, const float* dz32, const uint16_t* dz16,
+                            const float* in32, const uint16_t* in16, float* partial, float* out,
+                            int batch, int H, int W, hipStream_t stream);
+int cnn_wgrad_rows();
+
 // Direct FBP comparator kernels.
 hipError_t launch_direct_filter(const float* sino, float* work, int rows, int n_det,
-                                float weight, hipStream_t stream);
+                                float weight, const int* start, const float* wrow, int period,
+                                hipStream_t stream);
 hipError_t launch_direct_backproject(const float* work, float* img, int batch, int n,
-                                     int n_angles, int n_det, hipStream_t stream);
+                                     int n_rows, int n_det, const float* aff4,
+                                     hipStream_t stream);
 
 }  // namespace fhtfbp

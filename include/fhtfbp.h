@@ -202,6 +202,63 @@ const char* fbp_strerror(int code);
  * `cap` entries into levels[] and returns the pass count, or a negative error. */
 int fbp_plan_passes(fbp_plan_t plan, int32_t* levels, int32_t cap);
 
+/* ---- pass schedule (fusion depth) ----------------------------------------------------- */
+/* The back projection runs the log2 N butterfly levels of the transposed dyadic FHT (eq 19-21,
+ * Sec. 4.4) in a few HBM passes, each fusing a run of consecutive levels in on-chip memory.
+ * Every level performs the same pairwise additions whichever pass runs it, so the grouping
+ * and the column-tile width change the speed, never the result: images are bit-identical
+ * across schedules.
+ *
+ * fbp_plan_set_schedule replaces the grouping of fbp_reconstruct and fht_backproject:
+ * levels[0 .. passes-1] >= 1 must sum to log2 N (else FBP_EINVAL).  Pass 0, which also runs
+ * the filter, holds 2^levels[0] full rows in LDS (levels[0] <= first_max of
+ * fbp_plan_schedule_info, else FBP_ERANGE).  For N >= 256 the later passes work on tiles of
+ * 2^levels[i] rows by 2^log2w columns plus a halo; 6 <= log2w <= min(10, log2 N), 0 keeps the
+ * current width, and a tile that does not fit the LDS gives FBP_ERANGE.  Below N = 256 every
+ * pass holds full rows.  fht_forward keeps the plan's initial schedule.  When the new schedule
+ * needs more scratch than the plan holds, the call synchronises the plan's stream and
+ * allocates it (FBP_ENOMEM on failure, the schedule unchanged).  Graphs captured before the
+ * call refuse to launch (FBP_EINVAL) and must be captured again. */
+int fbp_plan_set_schedule(fbp_plan_t plan, const int32_t* levels, int32_t passes, int32_t log2w);
+
+/* Current column-tile width (log2) and the most levels pass 0 can fuse; either pointer may be
+ * NULL. */
+int fbp_plan_schedule_info(fbp_plan_t plan, int32_t* log2w, int32_t* first_max);
+
+/* ---- mixed batches and captured execution ------------------------------------------------ */
+typedef struct fbp_graph_s* fbp_graph_t;
+
+/* Reconstruct `count` sub-batches in one call (eq 9-13 then eq 19-22 per slice, as
+ * fbp_reconstruct): sub-batch i is batch[i] slices of plans[i]'s size, linogram lino[i] and
+ * image img[i] in the layouts above.  The plans may differ in N, order and coefficients, which
+ * makes a batch of mixed sizes one call.  Everything runs on `stream` (a HIP stream, NULL for
+ * the null stream) in sub-batch order; a plan that is profiling records its events there.
+ * All arguments are checked before anything is launched: count < 0, a NULL array, a NULL
+ * plan, a NULL or unaligned buffer of a non-empty sub-batch or plans on different devices give
+ * FBP_EINVAL, a batch above its plan's max_batch FBP_ERANGE.  count == 0 does nothing. */
+int fbp_reconstruct_many(const fbp_plan_t* plans, const float* const* lino, float* const* img,
+                         const int32_t* batch, int32_t count, void* stream);
+
+/* Capture the work of fbp_reconstruct_many with the same arguments into an executable HIP graph
+ * (*out), so that one fbp_graph_launch replays every kernel of every sub-batch with a single
+ * host call.  Sub-batches of distinct plans become parallel branches of the graph (each plan
+ * owns its scratch); sub-batches that share a plan run in order.  The graph keeps the buffer
+ * pointers given here and the plans' internal buffers: the plans must outlive it, and a
+ * launch must not overlap other work on the same plans.  Coefficient updates
+ * (fbp_plan_set_coefficients) are seen by later launches; a schedule change is not (the launch
+ * then fails with FBP_EINVAL).  Profiling events are not captured.  The capture uses streams
+ * and events of its own, destroyed before it returns.  FBP_EDEVICE if capture or
+ * instantiation fails.  count == 0 gives a graph whose launches do nothing. */
+int fbp_graph_create(const fbp_plan_t* plans, const float* const* lino, float* const* img,
+                     const int32_t* batch, int32_t count, fbp_graph_t* out);
+
+/* Enqueue one replay of the graph on `stream` (NULL: the null stream); returns without
+ * synchronising. */
+int fbp_graph_launch(fbp_graph_t graph, void* stream);
+
+/* Free the graph (NULL is a no-op).  Synchronise any stream it was launched on first. */
+int fbp_graph_destroy(fbp_graph_t graph);
+
 #ifdef __cplusplus
 }
 #endif

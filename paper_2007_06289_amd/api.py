@@ -94,6 +94,15 @@ def load_library():
         "fbp_strerror": ([ctypes.c_int], ctypes.c_char_p),
         "fbp_plan_profile": ([vp, i32], ctypes.c_int),
         "fbp_plan_profile_read": ([vp, dp, ctypes.POINTER(i32)], ctypes.c_int),
+        "fbp_plan_set_schedule": ([vp, ctypes.POINTER(i32), i32, i32], ctypes.c_int),
+        "fbp_plan_schedule_info": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32)],
+                                   ctypes.c_int),
+        "fbp_reconstruct_many": ([ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                  ctypes.POINTER(i32), i32, vp], ctypes.c_int),
+        "fbp_graph_create": ([ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                              ctypes.POINTER(i32), i32, ctypes.POINTER(vp)], ctypes.c_int),
+        "fbp_graph_launch": ([vp, vp], ctypes.c_int),
+        "fbp_graph_destroy": ([vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -179,6 +188,20 @@ class Plan:
         if p < 0:
             raise FbpError(p, "fbp_plan_passes")
         return [int(buf[i]) for i in range(p)]
+
+    def schedule(self) -> tuple[list[int], int, int]:
+        """(levels per back-projection pass, log2 of the column-tile width, most levels the
+        first pass can fuse)."""
+        w, f = ctypes.c_int32(), ctypes.c_int32()
+        _check(load_library().fbp_plan_schedule_info(self.handle, ctypes.byref(w),
+                                                     ctypes.byref(f)), "fbp_plan_schedule_info")
+        return self.passes(), int(w.value), int(f.value)
+
+    def set_schedule(self, levels, log2w: int = 0):
+        """Regroup the butterfly levels into passes (results are unchanged, bit for bit)."""
+        lv = (ctypes.c_int32 * len(levels))(*[int(x) for x in levels])
+        _check(load_library().fbp_plan_set_schedule(self.handle, lv, len(levels), int(log2w)),
+               "fbp_plan_set_schedule")
 
     KERNEL_KINDS = ("first", "middle", "last_v", "last_h", "forward", "filter")
 
@@ -425,3 +448,63 @@ def fbp_cnn_wgrad(cin: int, cout: int, dz: torch.Tensor, x: torch.Tensor) -> tor
                              _ptr(x) if cin == 16 else None, _ptr(partial), _ptr(out), B, H, W,
                              _stream_ptr()), "fbp_cnn_wgrad")
     return out
+
+
+def _many_args(plans, linos, imgs):
+    if not (len(plans) == len(linos) == len(imgs)):
+        raise ValueError("plans, linograms and images must have the same length")
+    k = len(plans)
+    P = (ctypes.c_void_p * max(k, 1))()
+    L = (ctypes.c_void_p * max(k, 1))()
+    I = (ctypes.c_void_p * max(k, 1))()
+    B = (ctypes.c_int32 * max(k, 1))()
+    for i, (p, lino, img) in enumerate(zip(plans, linos, imgs)):
+        b = _batch_of(lino, 3, f"lino[{i}]")
+        P[i] = p.handle.value
+        L[i] = _dev_ptr(lino, f"lino[{i}]", (b, 4, p.n, p.n)).value
+        I[i] = _dev_ptr(img, f"img[{i}]", (b, p.n, p.n)).value
+        B[i] = b
+    return P, L, I, B, k
+
+
+def fbp_reconstruct_many(plans, linos, imgs):
+    """Reconstruct a mixed batch: linos[i] [B_i,4,N_i,N_i] -> imgs[i] [B_i,N_i,N_i] with
+    plans[i], all on the current stream in one library call."""
+    P, L, I, B, k = _many_args(plans, linos, imgs)
+    _check(load_library().fbp_reconstruct_many(P, L, I, B, k, _stream_ptr()),
+           "fbp_reconstruct_many")
+    return imgs
+
+
+class Graph:
+    """A captured mixed-batch reconstruction (fbp_graph_create): ``launch()`` replays every
+    kernel with one call.  Keeps the plans and buffers alive while it exists."""
+
+    def __init__(self, plans, linos, imgs):
+        P, L, I, B, k = _many_args(plans, linos, imgs)
+        h = ctypes.c_void_p()
+        _check(load_library().fbp_graph_create(P, L, I, B, k, ctypes.byref(h)),
+               "fbp_graph_create")
+        self._h = h
+        self._keep = (list(plans), list(linos), list(imgs))
+
+    def launch(self):
+        if self._h is None:
+            raise RuntimeError("graph is destroyed")
+        _check(load_library().fbp_graph_launch(self._h, _stream_ptr()), "fbp_graph_launch")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            load_library().fbp_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fbp_graph_create(plans, linos, imgs) -> Graph:
+    return Graph(plans, linos, imgs)
+

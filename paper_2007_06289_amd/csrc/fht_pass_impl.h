@@ -254,6 +254,159 @@ __device__ void filter_tile(const PassArgs& A, float* S, int q, int row0) {
   __syncthreads();
 }
 
+// The same filter for rows stored window-aligned (window position p at LDS column p, skew period
+// 32): every in-chunk access is the chunk's base pointer plus an immediate offset.
+template <int K>
+__device__ void filter_tile_aligned(const PassArgs& A, float* S, int q, int row0) {
+  constexpr int L = 32;
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  const int C = 1 << A.log2c;
+  const int r = tid >> A.log2c, c = tid & (C - 1);
+  const int N = 1 << A.log2n;
+  const int t = row0 + r;
+  const int g = ((q * N + t) * A.groups) / (4 * N);
+  const float* cf = A.coef + (size_t)g * A.coef_stride;
+  float bk[K], ak[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    bk[k] = cf[k];
+    ak[k] = cf[K + k];
+  }
+  const float* phi = cf + 2 * K;
+  const float ct = A.scale[t];
+  const int base = c * L;
+  float* row = S + r * A.rs;
+  float* rp = row + base + (base >> 5);       // window positions base .. base + 31
+  auto at = [&](int p) -> float {             // halo sample, zero outside the window
+    const int pc = (p < 0 || p >= N) ? 0 : p;
+    const float v = row[pc + (pc >> 5)];
+    return (p >= 0 && p < N) ? v : 0.f;
+  };
+  float y[L];
+  float st[K], xs[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    st[k] = 0.f;
+    xs[k] = (k < K - 1) ? at(base - 1 - k) : 0.f;
+  }
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+#pragma unroll
+    for (int k = K - 1; k > 0; --k) xs[k] = xs[k - 1];
+    if ((i & 7) == 0) asm volatile("" ::: "memory");   // keeps at most 8 LDS reads in flight
+    xs[0] = rp[i];
+    float acc = 0.f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc = fmaf(bk[k], xs[k], acc);
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc = fmaf(-ak[k], st[k], acc);
+    y[i] = acc;
+#pragma unroll
+    for (int k = K - 1; k > 0; --k) st[k] = st[k - 1];
+    st[0] = acc;
+  }
+  {
+    float tv[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) tv[k] = st[k];
+    for (int j = 0; (1 << j) < C; ++j) {
+      const int d = 1 << j;
+      float u[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) u[k] = __shfl_up(tv[k], d, C);
+      if (c >= d) {
+        const float* P = phi + j * K * K;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          float acc = tv[k];
+#pragma unroll
+          for (int m = 0; m < K; ++m) acc = fmaf(P[k * K + m], u[m], acc);
+          tv[k] = acc;
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) st[k] = (C > 1) ? __shfl_up(tv[k], 1, C) : 0.f;
+    if (c == 0) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) st[k] = 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      float z = 0.f;
+#pragma unroll
+      for (int k = 0; k < K; ++k) z = fmaf(-ak[k], st[k], z);
+      y[i] += z;
+#pragma unroll
+      for (int k = K - 1; k > 0; --k) st[k] = st[k - 1];
+      st[0] = z;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    st[k] = 0.f;
+    xs[k] = (k < K - 1) ? at(base + L + k) : 0.f;
+  }
+#pragma unroll
+  for (int i = L - 1; i >= 0; --i) {
+#pragma unroll
+    for (int k = K - 1; k > 0; --k) xs[k] = xs[k - 1];
+    if ((i & 7) == 0) asm volatile("" ::: "memory");   // keeps at most 8 LDS reads in flight
+    xs[0] = rp[i];
+    float acc = 0.f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc = fmaf(bk[k], xs[k], acc);
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc = fmaf(-ak[k], st[k], acc);
+    y[i] += acc;
+#pragma unroll
+    for (int k = K - 1; k > 0; --k) st[k] = st[k - 1];
+    st[0] = acc;
+  }
+  {
+    float tv[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) tv[k] = st[k];
+    for (int j = 0; (1 << j) < C; ++j) {
+      const int d = 1 << j;
+      float u[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) u[k] = __shfl_down(tv[k], d, C);
+      if (c + d < C) {
+        const float* P = phi + j * K * K;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          float acc = tv[k];
+#pragma unroll
+          for (int m = 0; m < K; ++m) acc = fmaf(P[k * K + m], u[m], acc);
+          tv[k] = acc;
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) st[k] = (C > 1) ? __shfl_down(tv[k], 1, C) : 0.f;
+    if (c == C - 1) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) st[k] = 0.f;
+    }
+#pragma unroll
+    for (int i = L - 1; i >= 0; --i) {
+      float z = 0.f;
+#pragma unroll
+      for (int k = 0; k < K; ++k) z = fmaf(-ak[k], st[k], z);
+      y[i] += z;
+#pragma unroll
+      for (int k = K - 1; k > 0; --k) st[k] = st[k - 1];
+      st[0] = z;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < L; ++i) rp[i] = ct * y[i];
+  __syncthreads();
+}
+
 // ---- F in-place transposed butterfly levels with lazy shifts ---------------------------------
 // Streaming form (N >= 64): the work of a level is split into units (row pair, column segment
 // of W = N / S columns), S = max(1, waves / pairs), and every wave walks its units from the top
@@ -394,6 +547,139 @@ __device__ __forceinline__ void level_stream_fast(const PassArgs& A, float* S, f
       const float v2 = (y2 >= x0) ? t2 : below[unit * 64 + ((y2 - x0 + 64) & 63)];
       row0[x + (x >> 5)] = v0 + v1;
       row1[x + (x >> 5)] = v0 + v2;
+    }
+  }
+}
+
+// Streaming level for a tile whose rows start with the rotations sigma of their filtering
+// windows (ROT): the butterfly inputs then differ by d = (sigma_a - sigma_b) - J, which can be
+// positive.  Units with d <= 0 walk down from the top block with a copy of the 64 columns below
+// the segment; units with d >= 1 walk up from the bottom block with a copy of the 64 columns
+// above it.  Without ROT, d = -J (the plain lazy-shift form).
+template <int NBLK, bool ROT>
+__device__ __forceinline__ void level_stream_rot(const PassArgs& A, float* S, float* copy, int l,
+                                                 int row0) {
+  const int N = 1 << A.log2n, mask = N - 1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int waves = blockDim.x >> 6;
+  const int log2p = A.log2r - 1;
+  const int segs = waves > (1 << log2p) ? waves >> log2p : 1;
+  constexpr int W = NBLK * 64;
+  const int units = ((1 << log2p) * segs) / waves;
+  auto rel = [&](int pp, int J) -> int {
+    int d = -J;
+    if constexpr (ROT) {
+      const int sa = window_start_of(row0 + (pp << (l + 1)), A.log2n, A.windowed);
+      const int sb = window_start_of(row0 + (pp << (l + 1)) + (1 << l), A.log2n, A.windowed);
+      int delta = (sa - sb) & mask;
+      if (delta > (N >> 1)) delta -= N;
+      d += delta;
+    }
+    return d;
+  };
+  for (int u = 0; u < units; ++u) {
+    const int unit = wave + u * waves;
+    const int pair = unit / segs, seg = unit - pair * segs;
+    const int ib = pair & ((1 << l) - 1), pp = pair >> l;
+    const int r1 = ((pp << (l + 1)) | ib) | (1 << l);
+    const int d = rel(pp, brev_bits(ib, l));
+    const int xc = ((d <= 0) ? (seg * W - 64) : (seg * W + W)) + lane;
+    const int xm = xc & mask;
+    copy[unit * 64 + lane] = S[r1 * A.rs + xm + (xm >> 5)];
+  }
+  __syncthreads();
+  for (int u = 0; u < units; ++u) {
+    const int unit = wave + u * waves;
+    const int pair = unit / segs, seg = unit - pair * segs;
+    const int ib = pair & ((1 << l) - 1), pp = pair >> l;
+    const int r0 = (pp << (l + 1)) | ib, r1 = r0 | (1 << l);
+    const int d = rel(pp, brev_bits(ib, l));
+    float* row0p = S + r0 * A.rs;
+    float* row1p = S + r1 * A.rs;
+    const int x0 = seg * W;
+    const float* cp = copy + unit * 64;
+    if (d <= 0) {
+      const int xb = x0 + 64 + lane;              // block 1
+      const int x1 = xb + d, x2 = xb + d - 1;     // >= x0 since -d + 1 <= 64
+      float* a0 = row0p + xb + (xb >> 5);
+      float* w1 = row1p + xb + (xb >> 5);
+      const float* a1 = row1p + x1 + (x1 >> 5);
+      const float* a2 = row1p + x2 + (x2 >> 5);
+#pragma unroll
+      for (int top = NBLK - 1; top >= 1; top -= 4) {
+        float va[4], vb[4];
+#pragma unroll
+        for (int u2 = 0; u2 < 4; ++u2) {
+          const int k = top - u2;
+          if (k >= 1) {
+            const int off = 66 * (k - 1);
+            const float v0 = a0[off];
+            va[u2] = v0 + a1[off];
+            vb[u2] = v0 + a2[off];
+          }
+        }
+#pragma unroll
+        for (int u2 = 0; u2 < 4; ++u2) {
+          const int k = top - u2;
+          if (k >= 1) {
+            const int off = 66 * (k - 1);
+            a0[off] = va[u2];
+            w1[off] = vb[u2];
+          }
+        }
+      }
+      const int x = x0 + lane;
+      const int y1 = x + d, y2 = x + d - 1;
+      const int m1 = y1 & mask, m2 = y2 & mask;
+      const float v0 = row0p[x + (x >> 5)];
+      const float t1 = row1p[m1 + (m1 >> 5)];
+      const float t2 = row1p[m2 + (m2 >> 5)];
+      const float v1 = (y1 >= x0) ? t1 : cp[(y1 - x0 + 64) & 63];
+      const float v2 = (y2 >= x0) ? t2 : cp[(y2 - x0 + 64) & 63];
+      row0p[x + (x >> 5)] = v0 + v1;
+      row1p[x + (x >> 5)] = v0 + v2;
+    } else {
+      const int xb = x0 + lane;                   // block 0
+      const int x1 = xb + d, x2 = xb + d - 1;
+      float* a0 = row0p + xb + (xb >> 5);
+      float* w1 = row1p + xb + (xb >> 5);
+      const float* a1 = row1p + x1 + (x1 >> 5);
+      const float* a2 = row1p + x2 + (x2 >> 5);
+#pragma unroll
+      for (int bot = 0; bot <= NBLK - 2; bot += 4) {
+        float va[4], vb[4];
+#pragma unroll
+        for (int u2 = 0; u2 < 4; ++u2) {
+          const int k = bot + u2;
+          if (k <= NBLK - 2) {
+            const int off = 66 * k;
+            const float v0 = a0[off];
+            va[u2] = v0 + a1[off];
+            vb[u2] = v0 + a2[off];
+          }
+        }
+#pragma unroll
+        for (int u2 = 0; u2 < 4; ++u2) {
+          const int k = bot + u2;
+          if (k <= NBLK - 2) {
+            const int off = 66 * k;
+            a0[off] = va[u2];
+            w1[off] = vb[u2];
+          }
+        }
+      }
+      // top block: reads above the segment come from the copy
+      const int x = x0 + W - 64 + lane;
+      const int y1 = x + d, y2 = x + d - 1;
+      const int m1 = y1 & mask, m2 = y2 & mask;
+      const float v0 = row0p[x + (x >> 5)];
+      const float t1 = row1p[m1 + (m1 >> 5)];
+      const float t2 = row1p[m2 + (m2 >> 5)];
+      const int top_end = x0 + W;
+      const float v1 = (y1 < top_end) ? t1 : cp[(y1 - top_end) & 63];
+      const float v2 = (y2 < top_end) ? t2 : cp[(y2 - top_end) & 63];
+      row0p[x + (x >> 5)] = v0 + v1;
+      row1p[x + (x >> 5)] = v0 + v2;
     }
   }
 }
@@ -577,11 +863,19 @@ __global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
   float4 pre[NV];
   int tl = blockIdx.x;
   if (tl >= A.total_tiles) return;
+  // Tile loads go through a buffer resource: the tile base and the per-load step stay in scalar
+  // registers and every load shares one vector offset, so the prefetch holds only its data.
   auto issue = [&](int t2) {
     const int bq = t2 / tiles, v = t2 - bq * tiles;
-    const float4* src = reinterpret_cast<const float4*>(A.in + ((size_t)bq * N + (v << F)) * N);
+    const float* base = A.in + ((size_t)bq * N + (v << F)) * N;
+    const __amdgpu_buffer_rsrc_t rsrc =
+        __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (N << F) * 4, kBufferDword3);
 #pragma unroll
-    for (int k = 0; k < NV; ++k) pre[k] = src[tid + k * T];
+    for (int k = 0; k < NV; ++k) {
+      const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(rsrc, tid * 16, k * T * 16, 0);
+      pre[k] = make_float4(__uint_as_float(w.x), __uint_as_float(w.y), __uint_as_float(w.z),
+                           __uint_as_float(w.w));
+    }
   };
   issue(tl);
   for (; tl < A.total_tiles; tl += gridDim.x) {
@@ -589,31 +883,35 @@ __global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
     // are recomputed each iteration instead of being held in registers across the whole loop
     int ltid = tid;
     asm volatile("" : "+v"(ltid));
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      const int e4 = (ltid + k * T) << 2;
-      const int r = e4 >> A.log2n, x = e4 & mask;
-      float* d = S + r * A.rs;
-      d[x + (x >> A.log2l)] = pre[k].x;
-      d[x + 1 + ((x + 1) >> A.log2l)] = pre[k].y;
-      d[x + 2 + ((x + 2) >> A.log2l)] = pre[k].z;
-      d[x + 3 + ((x + 3) >> A.log2l)] = pre[k].w;
-    }
-    __syncthreads();
     const int bq = tl / tiles, v = tl - bq * tiles;
     const int q = bq & 3;
     const int row0 = v << F;
-    if constexpr (K > 0) filter_tile<L, K>(A, S, q, row0);
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const int e4 = (ltid + k * T) << 2;
+      const int r = e4 >> A.log2n;
+      // with the filter, row r is stored window-aligned: shift s at column s - sigma
+      const int x = (e4 - (K > 0 ? window_start_of(row0 + r, A.log2n, A.windowed) : 0)) & mask;
+      float* d = S + r * A.rs;
+      d[x + (x >> 5)] = pre[k].x;
+      const int x1 = (x + 1) & mask, x2 = (x + 2) & mask, x3 = (x + 3) & mask;
+      d[x1 + (x1 >> 5)] = pre[k].y;
+      d[x2 + (x2 >> 5)] = pre[k].z;
+      d[x3 + (x3 >> 5)] = pre[k].w;
+    }
+    __syncthreads();
+    if constexpr (K > 0) filter_tile_aligned<K>(A, S, q, row0);
     // the next tile's loads fly during the levels and the write-out of this one
     asm volatile("" ::: "memory");
     if (tl + (int)gridDim.x < A.total_tiles) issue(tl + gridDim.x);
     {
-      float* below = S + (1 << A.log2r) * A.rs;
+      float* copy = S + (1 << A.log2r) * A.rs;
       for (int l = 0; l < F; ++l) {
-        level_stream_fast<NBLK>(A, S, below, l);
+        level_stream_rot<NBLK, (K > 0)>(A, S, copy, l, row0);
         __syncthreads();
       }
     }
+    const int sig0 = (K > 0) ? window_start_of(row0, A.log2n, A.windowed) : 0;
     float* dst = A.out + (size_t)bq * N * N;
     int stid = tid;
     asm volatile("" : "+v"(stid));
@@ -621,7 +919,7 @@ __global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
       const int rho = (e << 2) >> A.log2n, x = (e << 2) & mask;
       const int i = brev_bits(rho, F);
       const int orow = (i << k_lo) + v;
-      const int o = (v * i) & mask;
+      const int o = (sig0 + v * i) & mask;
       float4 w;
       w.x = S[lds_at(rho, (x - o) & mask, A.rs, A.log2l)];
       w.y = S[lds_at(rho, (x + 1 - o) & mask, A.rs, A.log2l)];

@@ -21,7 +21,11 @@ struct fbp_plan_s {
   int cus = 0;                // compute units of the device
   int log2l = 0, log2c = 0;   // chunk length and chunks per row of the filter
   int rs = 0;                 // LDS row stride
-  std::vector<int> levels;    // levels per pass, first pass first
+  std::vector<int> levels;    // levels per back-projection pass, first pass first
+  std::vector<int> fwd_levels;   // levels per forward-transform pass (full-row tiles)
+  int log2w = 8;              // column-tiled passes: output columns per tile = 2^log2w
+  int fmax = 0;               // most levels a first pass (full rows in LDS) can fuse
+  unsigned generation = 0;    // bumped when the schedule changes (captured graphs go stale)
   std::vector<double> b, a;   // host copies [groups][order]
   int coef_stride = 0;
   float* d_coef = nullptr;
@@ -38,6 +42,13 @@ struct fbp_plan_s {
     int kind;
   };
   std::vector<Rec> recs;
+};
+
+// A captured reconstruction of one or more sub-batches (see fbp_graph_create).
+struct fbp_graph_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<std::pair<fbp_plan_s*, unsigned>> plans;   // distinct plans, schedule generation
 };
 
 namespace {
@@ -140,16 +151,24 @@ void clear_recs(fbp_plan_s* p) {
   p->recs.clear();
 }
 
-hipError_t dispatch(fbp_plan_s* p, const PassArgs& A, int batch, int family) {
-  if (family == PASS_COLS) return launch_cols(A, batch, p->stream);
-  if (family == PASS_FIRST) return launch_pass_kind(A, batch, PASS_FIRST, p->cus, p->stream);
-  return launch_pass(A, batch, p->stream);
+// Where and how a call's kernels are issued: the stream, and whether the plan's profiling
+// events may be recorded (never inside a graph capture).
+struct Issue {
+  hipStream_t stream;
+  bool timing;
+};
+Issue plan_issue(const fbp_plan_s* p) { return Issue{p->stream, p->profiling}; }
+
+hipError_t dispatch(fbp_plan_s* p, const PassArgs& A, int batch, int family, hipStream_t s) {
+  if (family == PASS_COLS) return launch_cols(A, batch, s);
+  if (family == PASS_FIRST) return launch_pass_kind(A, batch, PASS_FIRST, p->cus, s);
+  return launch_pass(A, batch, s);
 }
 
 // Launch one pass, bracketed by timing events when the plan is profiling.
-hipError_t timed_pass(fbp_plan_s* p, const PassArgs& A, int batch, int kind,
+hipError_t timed_pass(fbp_plan_s* p, const PassArgs& A, int batch, int kind, const Issue& is,
                       int family = PASS_ROWS) {
-  if (!p->profiling) return dispatch(p, A, batch, family);
+  if (!is.timing) return dispatch(p, A, batch, family, is.stream);
   fbp_plan_s::Rec r;
   r.kind = kind;
   if (hipEventCreate(&r.start) != hipSuccess) return hipErrorOutOfMemory;
@@ -157,9 +176,9 @@ hipError_t timed_pass(fbp_plan_s* p, const PassArgs& A, int batch, int kind,
     hipEventDestroy(r.start);
     return hipErrorOutOfMemory;
   }
-  hipEventRecord(r.start, p->stream);
-  hipError_t e = dispatch(p, A, batch, family);
-  hipEventRecord(r.stop, p->stream);
+  hipEventRecord(r.start, is.stream);
+  hipError_t e = dispatch(p, A, batch, family, is.stream);
+  hipEventRecord(r.stop, is.stream);
   p->recs.push_back(r);
   return e;
 }
@@ -183,6 +202,58 @@ int check_batch(const fbp_plan_s* p, int32_t batch) {
   return FBP_OK;
 }
 
+// Scratch buffers a schedule of P passes ping-pongs through.
+int scratch_needed(size_t passes) { return passes >= 3 ? 2 : (passes == 2 ? 1 : 0); }
+
+// Can the kernels run this back-projection schedule?  Pass 0 holds 2^F full rows (and runs the
+// filter); for N >= 256 the later passes are column-tiled (2^F rows of 2^log2w + halo columns,
+// two classes for the last pass), below that they hold full rows too.
+int check_schedule(const fbp_plan_s* p, const std::vector<int>& lv, int log2w) {
+  if (lv.empty() || lv.size() > 16) return FBP_EINVAL;
+  int sum = 0;
+  for (int F : lv) {
+    if (F < 1) return FBP_EINVAL;
+    sum += F;
+  }
+  if (sum != p->log2n) return FBP_EINVAL;
+  if (lv[0] > p->fmax) return FBP_ERANGE;
+  const bool cols = p->log2n >= 8;
+  if (cols && (log2w < 6 || log2w > std::min(10, p->log2n))) return FBP_ERANGE;
+  for (size_t i = 1; i < lv.size(); ++i) {
+    const int F = lv[i];
+    if (!cols) {
+      if (F > p->fmax) return FBP_ERANGE;
+      continue;
+    }
+    PassArgs t;
+    memset(&t, 0, sizeof(t));
+    t.log2n = p->log2n;
+    t.log2r = F;
+    t.log2w = log2w;
+    t.halo = std::max(4, 1 << F);
+    t.out_mode = (i + 1 == lv.size()) ? OUT_IMG_V : OUT_ROWS;
+    if (cols_lds_bytes(t) > (size_t)kLdsBudget) return FBP_ERANGE;
+  }
+  return FBP_OK;
+}
+
+// Arguments of a many-plan call, checked before anything is launched.
+int check_many(const fbp_plan_t* plans, const float* const* lino, float* const* img,
+               const int32_t* batch, int32_t count) {
+  if (count < 0) return FBP_EINVAL;
+  if (count == 0) return FBP_OK;
+  if (!plans || !lino || !img || !batch) return FBP_EINVAL;
+  for (int i = 0; i < count; ++i) {
+    const fbp_plan_s* p = plans[i];
+    if (!p || batch[i] < 0) return FBP_EINVAL;
+    if (batch[i] > p->max_batch) return FBP_ERANGE;
+    if (batch[i] > 0 && (!lino[i] || !img[i] || !aligned16(lino[i]) || !aligned16(img[i])))
+      return FBP_EINVAL;
+    if (p->device != plans[0]->device) return FBP_EINVAL;
+  }
+  return FBP_OK;
+}
+
 PassArgs base_args(const fbp_plan_s* p) {
   PassArgs A;
   memset(&A, 0, sizeof(A));
@@ -195,19 +266,21 @@ PassArgs base_args(const fbp_plan_s* p) {
   A.coef = p->d_coef;
   A.scale = p->d_scale;
   A.sigma = p->d_sigma;
+  A.windowed = (p->flags & FBP_ZERO_WINDOW) ? 0 : 1;
   return A;
 }
 
 // Run the transposed FHT passes.  forward: image -> linogram through the mirrored transform;
 // otherwise linogram -> image (with the filter fused into the first pass when `filter`).
 int run_passes(fbp_plan_s* p, const float* in, float* out, int batch, bool forward,
-               bool filter) {
+               bool filter, const Issue& is) {
   if (batch == 0) return FBP_OK;
-  const int P = (int)p->levels.size();
+  const std::vector<int>& levels = forward ? p->fwd_levels : p->levels;
+  const int P = (int)levels.size();
   int k = p->log2n;
   const float* src = in;
   for (int pi = 0; pi < P; ++pi) {
-    const int F = p->levels[pi];
+    const int F = levels[pi];
     const bool first = pi == 0, last = pi == P - 1;
     PassArgs A = base_args(p);
     A.levels = F;
@@ -221,7 +294,7 @@ int run_passes(fbp_plan_s* p, const float* in, float* out, int batch, bool forwa
     // column tiles for the middle and last back-projection passes (they carry no filter)
     const bool cols = !forward && !first && p->log2n >= 8;
     if (cols) {
-      A.log2w = std::min(8, p->log2n);
+      A.log2w = std::min(p->log2w, p->log2n);
       A.halo = std::max(4, 1 << F);
     }
     if (!last) {
@@ -229,26 +302,26 @@ int run_passes(fbp_plan_s* p, const float* in, float* out, int batch, bool forwa
       A.out = dst;
       A.out_mode = OUT_ROWS;
       if (cols) {
-        e = timed_pass(p, A, batch, kind, PASS_COLS);
+        e = timed_pass(p, A, batch, kind, is, PASS_COLS);
       } else if (first && !forward && p->log2l == 5 && pass_streams(A) &&
                  first_pass_supported(A)) {
         A.total_tiles = batch * 4 * (p->n >> F);
-        e = timed_pass(p, A, batch, kind, PASS_FIRST);
+        e = timed_pass(p, A, batch, kind, is, PASS_FIRST);
       } else {
-        e = timed_pass(p, A, batch, kind, PASS_ROWS);
+        e = timed_pass(p, A, batch, kind, is, PASS_ROWS);
       }
       src = dst;
     } else if (forward) {
       A.out = out;
       A.out_mode = OUT_LINO_MIRROR;
-      e = timed_pass(p, A, batch, kind, PASS_ROWS);
+      e = timed_pass(p, A, batch, kind, is, PASS_ROWS);
     } else {
       A.out = out;
       A.out_mode = OUT_IMG_V;
-      e = timed_pass(p, A, batch, FBP_KERNEL_LAST_V, cols ? PASS_COLS : PASS_ROWS);
+      e = timed_pass(p, A, batch, FBP_KERNEL_LAST_V, is, cols ? PASS_COLS : PASS_ROWS);
       if (e == hipSuccess) {
         A.out_mode = OUT_IMG_H;
-        e = timed_pass(p, A, batch, FBP_KERNEL_LAST_H, cols ? PASS_COLS : PASS_ROWS);
+        e = timed_pass(p, A, batch, FBP_KERNEL_LAST_H, is, cols ? PASS_COLS : PASS_ROWS);
       }
     }
     if (e != hipSuccess) return FBP_EDEVICE;
@@ -445,7 +518,9 @@ int fbp_plan(const fbp_plan_desc* d, fbp_plan_t* out) {
     delete p;
     return FBP_ERANGE;
   }
+  p->fmax = fmax;
   p->levels = split_levels(p->log2n, fmax);
+  p->fwd_levels = p->levels;
   {
     const int KK = kernel_order(K);
     p->coef_stride = 2 * KK + kScanLevels * KK * KK;
@@ -467,12 +542,11 @@ int fbp_plan(const fbp_plan_desc* d, fbp_plan_t* out) {
     if (p->flags & FBP_INPUT_IS_FHT) c *= k;
     if (p->flags & FBP_NO_ROW_SCALE) c = 1.0;
     scale[t] = (float)c;
-    const int start = (N - 1 - t) / 2 - N / 2;
-    sigma[t] = (p->flags & FBP_ZERO_WINDOW) ? 0 : ((start % N) + N) % N;
+    sigma[t] = window_start_of(t, p->log2n, (p->flags & FBP_ZERO_WINDOW) ? 0 : 1);
   }
   const size_t per_class = (size_t)N * N;
   p->scratch_floats = (size_t)p->max_batch * 4 * per_class;
-  const int nscratch = p->levels.size() >= 3 ? 2 : (p->levels.size() == 2 ? 1 : 0);
+  const int nscratch = scratch_needed(p->levels.size());
   bool ok = hipMalloc(&p->d_coef, (size_t)G * p->coef_stride * sizeof(float)) == hipSuccess &&
             hipMalloc(&p->d_scale, N * sizeof(float)) == hipSuccess &&
             hipMalloc(&p->d_sigma, N * sizeof(int)) == hipSuccess;
@@ -574,7 +648,7 @@ int fbp_filter(fbp_plan_t p, const float* in, float* out, int32_t batch) {
   A.in_mode = IN_ROWS;
   A.out_mode = OUT_SAME;
   A.order = kernel_order(p->order);
-  return timed_pass(p, A, batch, FBP_KERNEL_FILTER) == hipSuccess ? FBP_OK : FBP_EDEVICE;
+  return timed_pass(p, A, batch, FBP_KERNEL_FILTER, plan_issue(p)) == hipSuccess ? FBP_OK : FBP_EDEVICE;
 }
 
 int fht_backproject(fbp_plan_t p, const float* lino, float* img, int32_t batch) {
@@ -582,7 +656,7 @@ int fht_backproject(fbp_plan_t p, const float* lino, float* img, int32_t batch) 
   if (rc != FBP_OK) return rc;
   if (batch == 0) return FBP_OK;
   if (!lino || !img || !aligned16(lino) || !aligned16(img)) return FBP_EINVAL;
-  return run_passes(p, lino, img, batch, false, false);
+  return run_passes(p, lino, img, batch, false, false, plan_issue(p));
 }
 
 int fbp_reconstruct(fbp_plan_t p, const float* lino, float* img, int32_t batch) {
@@ -590,7 +664,7 @@ int fbp_reconstruct(fbp_plan_t p, const float* lino, float* img, int32_t batch) 
   if (rc != FBP_OK) return rc;
   if (batch == 0) return FBP_OK;
   if (!lino || !img || !aligned16(lino) || !aligned16(img)) return FBP_EINVAL;
-  return run_passes(p, lino, img, batch, false, true);
+  return run_passes(p, lino, img, batch, false, true, plan_issue(p));
 }
 
 int fht_forward(fbp_plan_t p, const float* img, float* lino, int32_t batch) {
@@ -598,7 +672,7 @@ int fht_forward(fbp_plan_t p, const float* img, float* lino, int32_t batch) {
   if (rc != FBP_OK) return rc;
   if (batch == 0) return FBP_OK;
   if (!lino || !img || !aligned16(lino) || !aligned16(img)) return FBP_EINVAL;
-  return run_passes(p, img, lino, batch, true, false);
+  return run_passes(p, img, lino, batch, true, false, plan_issue(p));
 }
 
 int fbp_direct_filter(const float* sino, float* work, int32_t batch, int32_t n_angles,
@@ -745,6 +819,128 @@ int fbp_direct_linogram(const float* lino, float* work, float* img, int32_t batc
   return launch_direct_backproject(work, img, batch, n, 4 * n, n, t->aff, s) == hipSuccess
              ? FBP_OK
              : FBP_EDEVICE;
+}
+
+int fbp_plan_set_schedule(fbp_plan_t p, const int32_t* levels, int32_t passes, int32_t log2w) {
+  if (!p || !levels || passes < 1) return FBP_EINVAL;
+  std::vector<int> lv(levels, levels + passes);
+  const int w = log2w == 0 ? p->log2w : log2w;
+  int rc = check_schedule(p, lv, w);
+  if (rc != FBP_OK) return rc;
+  const int have = scratch_needed(std::max(p->levels.size(), p->fwd_levels.size()));
+  const int need = scratch_needed(lv.size());
+  if (need > have) {
+    if (hipStreamSynchronize(p->stream) != hipSuccess) return FBP_EDEVICE;
+    for (int i = 0; i < need; ++i) {
+      if (p->d_scratch[i]) continue;
+      if (hipMalloc(&p->d_scratch[i], p->scratch_floats * sizeof(float)) != hipSuccess) {
+        p->d_scratch[i] = nullptr;
+        return FBP_ENOMEM;
+      }
+    }
+  }
+  p->levels = lv;
+  p->log2w = w;
+  p->generation += 1;
+  return FBP_OK;
+}
+
+int fbp_plan_schedule_info(fbp_plan_t p, int32_t* log2w, int32_t* first_max) {
+  if (!p) return FBP_EINVAL;
+  if (log2w) *log2w = p->log2w;
+  if (first_max) *first_max = p->fmax;
+  return FBP_OK;
+}
+
+int fbp_reconstruct_many(const fbp_plan_t* plans, const float* const* lino, float* const* img,
+                         const int32_t* batch, int32_t count, void* stream) {
+  int rc = check_many(plans, lino, img, batch, count);
+  if (rc != FBP_OK) return rc;
+  for (int i = 0; i < count; ++i) {
+    fbp_plan_s* p = plans[i];
+    rc = run_passes(p, lino[i], img[i], batch[i], false, true,
+                    Issue{(hipStream_t)stream, p->profiling});
+    if (rc != FBP_OK) return rc;
+  }
+  return FBP_OK;
+}
+
+int fbp_graph_create(const fbp_plan_t* plans, const float* const* lino, float* const* img,
+                     const int32_t* batch, int32_t count, fbp_graph_t* out) {
+  if (!out) return FBP_EINVAL;
+  *out = nullptr;
+  int rc = check_many(plans, lino, img, batch, count);
+  if (rc != FBP_OK) return rc;
+  fbp_graph_s* g = new (std::nothrow) fbp_graph_s();
+  if (!g) return FBP_ENOMEM;
+  // distinct plans, in order of first appearance: branch j of the graph runs plan j's work
+  std::vector<int> branch(count);
+  for (int i = 0; i < count; ++i) {
+    int j = 0;
+    while (j < (int)g->plans.size() && g->plans[j].first != plans[i]) ++j;
+    if (j == (int)g->plans.size()) g->plans.emplace_back(plans[i], plans[i]->generation);
+    branch[i] = j;
+  }
+  if (count == 0) {   // an empty graph: launches do nothing
+    *out = g;
+    return FBP_OK;
+  }
+  const int D = (int)g->plans.size();
+  std::vector<hipStream_t> st(D, nullptr);
+  std::vector<hipEvent_t> ev(D, nullptr);   // ev[0]: fork, ev[j >= 1]: join of branch j
+  bool ok = true;
+  for (int j = 0; ok && j < D; ++j)
+    ok = hipStreamCreateWithFlags(&st[j], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&ev[j], hipEventDisableTiming) == hipSuccess;
+  if (ok) ok = hipStreamBeginCapture(st[0], hipStreamCaptureModeThreadLocal) == hipSuccess;
+  const bool capturing = ok;
+  if (ok && D > 1) {
+    ok = hipEventRecord(ev[0], st[0]) == hipSuccess;
+    for (int j = 1; ok && j < D; ++j) ok = hipStreamWaitEvent(st[j], ev[0], 0) == hipSuccess;
+  }
+  for (int i = 0; ok && i < count; ++i)
+    ok = run_passes(plans[i], lino[i], img[i], batch[i], false, true,
+                    Issue{st[branch[i]], false}) == FBP_OK;
+  for (int j = 1; ok && j < D; ++j)
+    ok = hipEventRecord(ev[j], st[j]) == hipSuccess &&
+         hipStreamWaitEvent(st[0], ev[j], 0) == hipSuccess;
+  if (capturing) {
+    hipGraph_t graph = nullptr;
+    const bool ended = hipStreamEndCapture(st[0], &graph) == hipSuccess;
+    if (ok && ended) {
+      g->graph = graph;
+      ok = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) == hipSuccess;
+    } else {
+      ok = false;
+      if (graph) hipGraphDestroy(graph);
+    }
+  }
+  for (int j = 0; j < D; ++j) {
+    if (ev[j]) hipEventDestroy(ev[j]);
+    if (st[j]) hipStreamDestroy(st[j]);
+  }
+  if (!ok) {
+    fbp_graph_destroy(g);
+    return FBP_EDEVICE;
+  }
+  *out = g;
+  return FBP_OK;
+}
+
+int fbp_graph_launch(fbp_graph_t g, void* stream) {
+  if (!g) return FBP_EINVAL;
+  for (auto& pg : g->plans)
+    if (pg.first->generation != pg.second) return FBP_EINVAL;   // schedule changed since capture
+  if (!g->exec) return FBP_OK;
+  return hipGraphLaunch(g->exec, (hipStream_t)stream) == hipSuccess ? FBP_OK : FBP_EDEVICE;
+}
+
+int fbp_graph_destroy(fbp_graph_t g) {
+  if (!g) return FBP_OK;
+  if (g->exec) hipGraphExecDestroy(g->exec);
+  if (g->graph) hipGraphDestroy(g->graph);
+  delete g;
+  return FBP_OK;
 }
 
 }  // extern "C"

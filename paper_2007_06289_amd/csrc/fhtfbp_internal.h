@@ -47,7 +47,19 @@ struct PassArgs {
   int log2w;           // column-tiled passes: output columns per tile = 2^log2w
   int halo;            // column-tiled passes: extra columns loaded below the tile (>= 2^F - 1)
   int total_tiles;     // persistent passes: tiles over the whole batch
+  int windowed;        // 1: rows start at the window start below, 0: at shift 0
 };
+
+// Fourth word of a raw buffer resource on gfx9-family devices (32-bit data, no swizzle).
+constexpr int kBufferDword3 = 0x00020000;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Window start of row t (the same values as the `sigma` table): the window is centred on
+// floor((N-1-t)/2), the intercept of the row's central line, and begins N/2 shifts below it.
+__host__ __device__ inline int window_start_of(int t, int log2n, int windowed) {
+  const int N = 1 << log2n;
+  return windowed ? ((((N - 1 - t) >> 1) - (N >> 1)) & (N - 1)) : 0;
+}
 
 // Launch one pass over `batch` slices on `stream`.  Returns hipSuccess or the launch error.
 // `a.order` is the kernel order: 0 (no filter), 1..4 or 8 (orders 5..7 zero-padded to 8).

@@ -122,8 +122,12 @@ class FBPWithCoefficients(torch.autograd.Function):
 
 
 class LearnedFBP:
-    """Per-angle-group order-K coefficients (b free, a through reflection coefficients) and
-    the residual network."""
+    """Per-angle-group order-K coefficients and the residual network.
+
+    a goes through reflection coefficients (always stable).  b is free up to the constraint
+    sum(b) = 0 for K > 1: the ramp response vanishes at zero frequency (eq 6), so the recursive
+    pair keeps a zero DC gain, which the fit of the plain method also imposes.  Without it the
+    DC gain of the learned filter drifts and scales the whole image by a constant offset."""
 
     def __init__(self, n: int, max_batch: int, order: int = 4, groups: int = 8,
                  cnn: bool = True, seed: int = 0, fit_length: int | None = None):
@@ -141,7 +145,8 @@ class LearnedFBP:
 
     def coefficients(self):
         a = step_up(RMAX * torch.tanh(self.theta))
-        return self.b, a
+        b = self.b - self.b.mean(dim=1, keepdim=True) if self.order > 1 else self.b
+        return b, a
 
     def __call__(self, lino: torch.Tensor) -> torch.Tensor:
         b, a = self.coefficients()

@@ -41,7 +41,175 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (for scaling the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-size batch (64 slices, N from {256, 512, 1024, 2048})")
+    ap.add_argument("--tune", action="store_true",
+                    help="search the pass schedule first (cached per device and shape)")
+    ap.add_argument("--rocprof-summary", metavar="DIR",
+                    help="summarise rocprofv3 csv output under DIR (subfolders trace, fetch, "
+                         "write, copyf, copyw, sq) as text for the profiles folder, and exit")
+    ap.add_argument("--profile", default=None,
+                    help="profile summary whose HBM counters fill roofline.traffic when its "
+                         "kernel-source hash matches (default: the one for this workload)")
     return ap.parse_args()
+
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+KIND_OF_KERNEL = (("fht_first_kernel", "first"), ("fht_cols_kernel<2>", "last"),
+                  ("fht_cols_kernel<1>", "middle"), ("fht_rows_kernel", "rows"),
+                  ("fht_combine_kernel", "combine"))
+
+
+def kernel_source_hash() -> str:
+    """sha256 (16 hex digits) of the HIP sources and headers the pass kernels are built from."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2007_06289_amd", "csrc")
+    for fn in sorted(os.listdir(d)):
+        if fn.endswith((".hip", ".h", ".cpp")):
+            h.update(fn.encode())
+            h.update(open(os.path.join(d, fn), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def default_profile_path(n: int, batch: int, order: int) -> str:
+    return os.path.join(ROOT, "profiles", f"fht_fbp_n{n}_b{batch}_order{order}.txt")
+
+
+def _kind(name: str):
+    for key, kind in KIND_OF_KERNEL:
+        if key in name:
+            return kind
+    return None
+
+
+def rocprof_summary(d: str, n: int, batch: int, order: int) -> str:
+    """Text summary of a rocprofv3 run set: per-kernel durations (kernel trace) and HBM bytes per
+    dispatch (FETCH_SIZE / WRITE_SIZE, scaled by what the same counters read for a plain copy
+    of known size), plus SQ counters.  The last pass kernel runs twice per step (classes 0+1,
+    then 2+3): its dispatches alternate last_v, last_h."""
+    import csv
+    import glob
+    from collections import defaultdict
+
+    def rows(pattern):
+        out = []
+        for f in sorted(glob.glob(os.path.join(d, pattern))):
+            with open(f) as fh:
+                out += list(csv.DictReader(fh))
+        return out
+
+    def split_last(kind, seq):
+        return [("last_v" if i % 2 == 0 else "last_h") if kind == "last" else kind
+                for i, _ in enumerate(seq)]
+
+    lines = []
+    res = {"n": n, "batch": batch, "order": order, "kernel_source_hash": kernel_source_hash(),
+           "kernels": {}}
+    # durations per dispatch, in launch order
+    tr = rows("trace/*kernel_trace.csv")
+    tr.sort(key=lambda r: int(r["Start_Timestamp"]))
+    per = defaultdict(list)
+    seqs = defaultdict(list)
+    for r in tr:
+        k = _kind(r["Kernel_Name"])
+        if k:
+            seqs[k].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    for k, v in seqs.items():
+        for kk, dur in zip(split_last(k, v), v):
+            per[kk].append(dur)
+    lines.append("kernel trace (rocprofv3 --kernel-trace --stats), this workload's pass kernels:")
+    lines.append(f"  {'kernel':8s} {'dispatches':>10s} {'avg_us':>10s} {'min_us':>10s} "
+                 f"{'max_us':>10s}")
+    for k, v in sorted(per.items()):
+        avg = sum(v) / len(v) / 1e3
+        lines.append(f"  {k:8s} {len(v):10d} {avg:10.1f} {min(v) / 1e3:10.1f} "
+                     f"{max(v) / 1e3:10.1f}")
+        res["kernels"].setdefault(k, {})["avg_us"] = round(avg, 2)
+        res["kernels"][k]["dispatches"] = len(v)
+    st = rows("trace/*kernel_stats.csv")
+    tot = sum(float(r.get("TotalDurationNs", 0)) for r in st)
+    ours = sum(float(r.get("TotalDurationNs", 0)) for r in st if _kind(r.get("Name", "")))
+    if tot:
+        lines.append(f"  pass kernels: {100 * ours / tot:.1f}% of all GPU kernel time in the run "
+                     "(the rest is input generation and checks)")
+
+    def counter(tag, cname):
+        agg = defaultdict(list)
+        for r in rows(f"{tag}/*counter_collection.csv"):
+            if r.get("Counter_Name") != cname:
+                continue
+            agg[r["Kernel_Name"]].append((int(r.get("Dispatch_Id", 0)),
+                                          float(r["Counter_Value"])))
+        return agg
+
+    def copy_kib(tag, cname):
+        vals = []
+        for name, v in counter(tag, cname).items():
+            if "copy" in name.lower() or "elementwise" in name.lower():
+                vals += [x for _, x in v]
+        return max(vals) if vals else None
+
+    gib = float(1 << 30)
+    cf, cw = copy_kib("copyf", "FETCH_SIZE"), copy_kib("copyw", "WRITE_SIZE")
+    if cf and cw:
+        ff, fw = gib / (cf * 1024), gib / (cw * 1024)
+        res["copy_factor"] = {"fetch": round(ff, 4), "write": round(fw, 4)}
+        lines.append(f"copy calibration (1 GiB device copy): FETCH_SIZE {cf:.0f} KiB, WRITE_SIZE "
+                     f"{cw:.0f} KiB per dispatch -> scale factors fetch x{ff:.3f}, write x{fw:.3f}")
+        alg = {"first": 32, "middle": 32, "last_v": 12, "last_h": 16}
+        lines.append("HBM bytes per dispatch (counters x factor) vs algorithmic bytes:")
+        for cname, tag, fac in (("FETCH_SIZE", "fetch", ff), ("WRITE_SIZE", "write", fw)):
+            by = defaultdict(list)
+            for name, v in counter(tag, cname).items():
+                k = _kind(name)
+                if not k:
+                    continue
+                v.sort()
+                for kk, (_, x) in zip(split_last(k, v), v):
+                    by[kk].append(x)
+            for k, v in by.items():
+                res["kernels"].setdefault(k, {})[cname.lower() + "_bytes"] =                     round(sum(v) / len(v) * 1024 * fac)
+        for k, kv in sorted(res["kernels"].items()):
+            if "fetch_size_bytes" in kv and "write_size_bytes" in kv:
+                t = kv["fetch_size_bytes"] + kv["write_size_bytes"]
+                kv["hbm_bytes"] = t
+                a = alg.get(k, 0) * float(n) * n * batch
+                kv["algorithmic_bytes"] = round(a)
+                lines.append(f"  {k:8s} read {kv['fetch_size_bytes'] / 1e9:8.3f} GB  write "
+                             f"{kv['write_size_bytes'] / 1e9:8.3f} GB  total {t / 1e9:8.3f} GB  "
+                             f"algorithmic {a / 1e9:8.3f} GB  ratio {t / a if a else 0:6.3f}")
+    sq = defaultdict(lambda: defaultdict(list))
+    for r in rows("sq/*counter_collection.csv"):
+        k = _kind(r["Kernel_Name"])
+        if k:
+            sq[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    if sq:
+        lines.append("SQ counters, mean per dispatch:")
+        for k, cs in sorted(sq.items()):
+            lines.append(f"  {k:8s} " + "  ".join(f"{c}={sum(v) / len(v):.4g}"
+                                                  for c, v in sorted(cs.items())))
+            res["kernels"].setdefault(k, {})["sq"] = {c: sum(v) / len(v) for c, v in cs.items()}
+    lines.append("JSON " + json.dumps(res, sort_keys=True))
+    return "\n".join(lines)
+
+
+def traffic_from_profile(path: str, kind: str):
+    """HBM bytes per launch of `kind` from a committed profile summary, or None when the summary
+    is missing or was taken on other kernel sources."""
+    if not path or not os.path.exists(path):
+        return None, "no profile summary"
+    js = None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("JSON "):
+                js = json.loads(line[5:])
+    if js is None:
+        return None, "profile summary has no JSON line"
+    if js.get("kernel_source_hash") != kernel_source_hash():
+        return None, "kernels changed since the counters were taken"
+    kv = js.get("kernels", {}).get(kind, {})
+    return kv.get("hbm_bytes"), os.path.relpath(path, ROOT)
 
 
 def copy_calibration():
@@ -68,6 +236,49 @@ def algorithmic_bytes(kind: str, n: int, levels: list[int]) -> float:
             "forward": 20 * n2, "filter": 32 * n2}[kind]
 
 
+def mixed_batch(F, I, b, a, reps: int = 10):
+    """64 slices with N drawn from {256, 512, 1024, 2048} (seed 4), one plan per size: the
+    eager many-plan call against one captured-graph launch per batch (sizes run as parallel
+    branches of the graph)."""
+    import numpy as np
+    import torch
+    sizes = np.random.default_rng(4).choice([256, 512, 1024, 2048], size=64)
+    plans, linos, imgs, counts = [], [], [], {}
+    for k, n in enumerate(sorted(set(int(x) for x in sizes))):
+        c = int((sizes == n).sum())
+        counts[n] = c
+        ells = I.random_ellipses(n, 30, seed=40 + k, batch=c)
+        linos.append(I.linogram(ells, n, device="cuda", dtype=torch.float32, chunk=8))
+        imgs.append(torch.empty((c, n, n), device="cuda"))
+        bn, an, _ = F.fbp_fit_ramp_iir(len(b), n, dc_zero=len(b) > 1)
+        plans.append(F.fbp_plan(n, c, bn, an))
+    eager = [torch.empty_like(x) for x in imgs]
+    g = F.fbp_graph_create(plans, linos, imgs)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    F.fbp_reconstruct_many(plans, linos, eager)
+    g.launch()
+    torch.cuda.synchronize()
+    same = all(torch.equal(x, y) for x, y in zip(imgs, eager))
+    ev[0].record()
+    for _ in range(reps):
+        F.fbp_reconstruct_many(plans, linos, eager)
+    ev[1].record()
+    for _ in range(reps):
+        g.launch()
+    ev[2].record()
+    torch.cuda.synchronize()
+    t_eager = ev[0].elapsed_time(ev[1]) / reps
+    t_graph = ev[1].elapsed_time(ev[2]) / reps
+    g.close()
+    for p in plans:
+        p.close()
+    return {"slices": 64, "counts_by_n": {str(k): v for k, v in counts.items()},
+            "eager_ms": round(t_eager, 3), "graph_ms": round(t_graph, 3),
+            "slices_per_s_graph": round(64 / (t_graph * 1e-3), 1),
+            "slices_per_s_eager": round(64 / (t_eager * 1e-3), 1),
+            "graph_equals_eager": bool(same)}
+
+
 def cpu_baseline(lino_cpu, b, a):
     """The FP64 oracle (as it stands) on a bounded sample of slices, on the host's cores."""
     import torch
@@ -92,6 +303,9 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
+    if args.rocprof_summary:
+        print(rocprof_summary(args.rocprof_summary, args.n, args.batch, args.order))
+        return
     import torch
     import fbp_inputs as I
     import paper_2007_06289_amd as F
@@ -112,6 +326,11 @@ def main():
 
     plan = F.fbp_plan(N, B, b, a)
     img = torch.empty((B, N, N), device=dev, dtype=torch.float32)
+    tuned = None
+    if args.tune:
+        from paper_2007_06289_amd import autotune
+        tuned = autotune.tune(plan, lino, reps=3)
+        print(f"[bench] schedule {tuned}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         F.fbp_reconstruct(plan, lino, img)
     torch.cuda.synchronize()
@@ -145,9 +364,13 @@ def main():
                          "GB_per_s": byt / (avg * 1e-3) / 1e9}
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
     dk = kernels[dom]
+    traffic, tsrc = traffic_from_profile(
+        args.profile or default_profile_path(N, B, args.order), dom)
     roofline = {"bound": "hbm", "kernel": f"fht pass ({dom})", "achieved": round(dk["GB_per_s"], 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dk["GB_per_s"] / HBM_PEAK_GBS, 4),
-                "traffic": None}
+                "traffic": None if traffic is None else round(traffic / 1e9, 3),
+                "traffic_unit": "GB per launch", "traffic_source": tsrc,
+                "algorithmic_GB_per_launch": round(dk["algorithmic_GB"], 3)}
     path_gbs = 20.0 * N * N * B / (ms_step * 1e-3) / 1e9
 
     out = {
@@ -165,7 +388,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"volume of {B} slices, N={N}, 30 random ellipsoids, "
                                f"order-{args.order} recursive ramp pair, fbp_reconstruct",
-                   "n": N, "batch": B, "order": args.order, "passes": levels},
+                   "n": N, "batch": B, "order": args.order, "passes": levels,
+                   "schedule": "tuned" if tuned else "default"},
         "roofline": roofline,
         "kernels": {k: {kk: round(vv, 4) if isinstance(vv, float) else vv
                         for kk, vv in v.items()} for k, v in kernels.items()},
@@ -209,6 +433,11 @@ def main():
                                  round(slices_per_s / (nd / (t_b * 1e-3)), 1),
                              "rel_rmse_fht_vs_direct": round(rmse, 5)}
         del sino, work, dimg
+
+    # ---- mixed-size batch: eager many-plan call vs one graph launch ------------------------------
+    if not args.no_mixed:
+        out["mixed_batch"] = mixed_batch(F, I, b, a)
+        print(f"[bench] mixed batch {out['mixed_batch']}", file=sys.stderr, flush=True)
 
     # ---- CPU oracle on a bounded sample (also gives the FP32-vs-FP64 RMSE) ---------------------
     if not args.no_cpu:

@@ -939,21 +939,46 @@ __global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
 // one class, rows written with their pending rotation.
 __device__ __forceinline__ int cat(int r, int c, int rs) { return r * rs + c + (c >> 5); }
 
-__device__ void cols_load(const PassArgs& A, float* S, int rs, const float* cls, int row0,
-                          int xs) {
+// Load a tile of 2^log2r rows by 2^log2w + halo columns from each of `ncls` classes (class 0 from
+// c0 starting at column xs0, class 1 from c1 at xs1, cyclically) into skewed LDS rows.  Loads go
+// out in batches, so each thread has up to kColBatch float4 loads in flight before it stores any.
+constexpr int kColBatch = 12;
+__device__ void cols_load_batched(const PassArgs& A, float* S, int rs, int ncls, const float* c0,
+                                  int xs0, const float* c1, int xs1, int row0) {
   const int N = 1 << A.log2n, mask = N - 1;
   const int R = 1 << A.log2r;
   const int wt = (1 << A.log2w) + A.halo;
   const int nv = wt >> 2;                      // float4 per row
-  for (int e = threadIdx.x; e < R * nv; e += blockDim.x) {
-    const int r = e / nv, c4 = (e - r * nv) << 2;
-    const float4 v = *reinterpret_cast<const float4*>(cls + (size_t)(row0 + r) * N +
-                                                       ((xs + c4) & mask));
-    float* d = S + r * rs;
-    d[c4 + (c4 >> 5)] = v.x;
-    d[c4 + 1 + ((c4 + 1) >> 5)] = v.y;
-    d[c4 + 2 + ((c4 + 2) >> 5)] = v.z;
-    d[c4 + 3 + ((c4 + 3) >> 5)] = v.w;
+  const int per = R * nv, total = ncls * per;
+  const int T = blockDim.x;
+  for (int base = threadIdx.x; base < total; base += kColBatch * T) {
+    float4 v[kColBatch];
+#pragma unroll
+    for (int k = 0; k < kColBatch; ++k) {
+      const int e = base + k * T;
+      if (e < total) {
+        const int cl = e >= per ? 1 : 0;
+        const int ee = e - cl * per;
+        const int r = ee / nv, c4 = (ee - r * nv) << 2;
+        const float* src = cl ? c1 : c0;
+        const int xs = cl ? xs1 : xs0;
+        v[k] = *reinterpret_cast<const float4*>(src + (size_t)(row0 + r) * N + ((xs + c4) & mask));
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kColBatch; ++k) {
+      const int e = base + k * T;
+      if (e < total) {
+        const int cl = e >= per ? 1 : 0;
+        const int ee = e - cl * per;
+        const int r = ee / nv, c4 = (ee - r * nv) << 2;
+        float* d = S + (cl * R + r) * rs;
+        d[c4 + (c4 >> 5)] = v[k].x;
+        d[c4 + 1 + ((c4 + 1) >> 5)] = v[k].y;
+        d[c4 + 2 + ((c4 + 2) >> 5)] = v[k].z;
+        d[c4 + 3 + ((c4 + 3) >> 5)] = v[k].w;
+      }
+    }
   }
 }
 
@@ -1072,8 +1097,24 @@ __global__ void __launch_bounds__(512) fht_cols_kernel(PassArgs A) {
     const int row0 = j * R;
     const float* c0 = A.in + ((size_t)b * 4 + qa) * N * N;
     const float* c1 = c0 + (size_t)N * N;
-    cols_load(A, S, rs, c0, row0, (cx - H) & mask);
-    cols_load(A, S + R * rs, rs, c1, row0, (N - cx - W - H) & mask);
+    float* img = A.out + (size_t)b * N * N;
+    const bool hpass = A.out_mode == OUT_IMG_H;
+    const bool vec = R >= 4;                      // float4 image access along i (H) or u (V)
+    const int n4 = (R * W) >> 2;
+    cols_load_batched(A, S, rs, 2, c0, (cx - H) & mask, c1, (N - cx - W - H) & mask, row0);
+    // the H pass adds into image values that do not depend on the levels: load them now
+    constexpr int kOld = 8;
+    float4 old[kOld];
+    if (hpass && vec) {
+#pragma unroll
+      for (int k = 0; k < kOld; ++k) {
+        const int e4 = tid + k * T;
+        if (e4 < n4) {
+          const int i4 = (e4 & ((R >> 2) - 1)) << 2, u = e4 >> (A.log2r - 2);
+          old[k] = *reinterpret_cast<const float4*>(img + (size_t)(cx + u) * N + row0 + i4);
+        }
+      }
+    }
     __syncthreads();
     const int pad = 64 * ((wt + 63) >> 6) - wt;
     for (int l = 0; l < F; ++l) {
@@ -1083,8 +1124,41 @@ __global__ void __launch_bounds__(512) fht_cols_kernel(PassArgs A) {
     }
     const float* s0 = S;
     const float* s1 = S + R * rs;
-    float* img = A.out + (size_t)b * N * N;
-    if (A.out_mode == OUT_IMG_V) {
+    if (vec && !hpass) {
+      // image[j R + i][cx + u] = c0[i][cx + u] + c1[i][N - 1 - cx - u], four u per thread
+      for (int e4 = tid; e4 < n4; e4 += T) {
+        const int i = e4 >> (A.log2w - 2), u = (e4 & ((W >> 2) - 1)) << 2;
+        const int rho = brev_bits(i, F);
+        float4 w;
+        w.x = s0[cat(rho, H + u, rs)] + s1[cat(rho, H + W - 1 - u, rs)];
+        w.y = s0[cat(rho, H + u + 1, rs)] + s1[cat(rho, H + W - 2 - u, rs)];
+        w.z = s0[cat(rho, H + u + 2, rs)] + s1[cat(rho, H + W - 3 - u, rs)];
+        w.w = s0[cat(rho, H + u + 3, rs)] + s1[cat(rho, H + W - 4 - u, rs)];
+        *reinterpret_cast<float4*>(img + (size_t)(row0 + i) * N + cx + u) = w;
+      }
+    } else if (vec) {
+      // image[cx + u][j R + i] += c2[i][cx + u] + c3[i][N - 1 - cx - u], four i per thread
+      auto add4 = [&](int e4, float4 o) {
+        const int i = (e4 & ((R >> 2) - 1)) << 2, u = e4 >> (A.log2r - 2);
+        const int r0 = brev_bits(i, F), r1 = brev_bits(i + 1, F);
+        const int r2 = brev_bits(i + 2, F), r3 = brev_bits(i + 3, F);
+        float4 w;
+        w.x = o.x + s0[cat(r0, H + u, rs)] + s1[cat(r0, H + W - 1 - u, rs)];
+        w.y = o.y + s0[cat(r1, H + u, rs)] + s1[cat(r1, H + W - 1 - u, rs)];
+        w.z = o.z + s0[cat(r2, H + u, rs)] + s1[cat(r2, H + W - 1 - u, rs)];
+        w.w = o.w + s0[cat(r3, H + u, rs)] + s1[cat(r3, H + W - 1 - u, rs)];
+        *reinterpret_cast<float4*>(img + (size_t)(cx + u) * N + row0 + i) = w;
+      };
+#pragma unroll
+      for (int k = 0; k < kOld; ++k) {
+        const int e4 = tid + k * T;
+        if (e4 < n4) add4(e4, old[k]);
+      }
+      for (int e4 = tid + kOld * T; e4 < n4; e4 += T) {
+        const int i = (e4 & ((R >> 2) - 1)) << 2, u = e4 >> (A.log2r - 2);
+        add4(e4, *reinterpret_cast<const float4*>(img + (size_t)(cx + u) * N + row0 + i));
+      }
+    } else if (A.out_mode == OUT_IMG_V) {
       // image[j R + i][cx + u] = c0[i][cx + u] + c1[i][N - 1 - cx - u]
       for (int e = tid; e < R * W; e += T) {
         const int i = e >> A.log2w, u = e & (W - 1);
@@ -1109,7 +1183,7 @@ __global__ void __launch_bounds__(512) fht_cols_kernel(PassArgs A) {
     const int row0 = (j << A.k_hi) + (v << F);
     const int k_lo = A.k_hi - F;
     const float* cls = A.in + (size_t)bq * N * N;
-    cols_load(A, S, rs, cls, row0, (cx - H) & mask);
+    cols_load_batched(A, S, rs, 1, cls, (cx - H) & mask, cls, 0, row0);
     __syncthreads();
     const int pad = 64 * ((wt + 63) >> 6) - wt;
     for (int l = 0; l < F; ++l) {

@@ -86,3 +86,28 @@ def test_host_fit_matches_the_ramp_half(order, dc0, bound):
         assert abs(b.sum()) < 1e-12
     # stable: all poles inside the unit circle
     assert np.abs(np.roots(np.concatenate([[1.0], a]))).max() < 1.0
+
+
+def test_schedule_and_graph_entry_points_reject_bad_arguments(lib):
+    assert lib.fbp_plan_set_schedule(None, None, 0, 0) == -1
+    assert lib.fbp_plan_schedule_info(None, None, None) == -1
+    # an empty mixed batch is a no-op and needs no device
+    assert lib.fbp_reconstruct_many(None, None, None, None, 0, None) == 0
+    assert lib.fbp_reconstruct_many(None, None, None, None, -1, None) == -1
+    assert lib.fbp_reconstruct_many(None, None, None, None, 2, None) == -1
+    assert lib.fbp_graph_create(None, None, None, None, 0, None) == -1
+    assert lib.fbp_graph_launch(None, None) == -1
+    assert lib.fbp_graph_destroy(None) == 0
+
+
+def test_schedule_candidates_are_all_compositions():
+    from math import comb
+
+    from paper_2007_06289_amd.autotune import compositions
+    for total in range(1, 13):
+        for parts in range(1, 5):
+            got = compositions(total, parts, total)
+            assert len(got) == len(set(got))
+            assert all(sum(c) == total and 1 <= len(c) <= parts for c in got)
+            assert len(got) == sum(comb(total - 1, j - 1) for j in range(1, parts + 1))
+    assert all(max(c) <= 3 for c in compositions(10, 4, 3))

@@ -25,6 +25,14 @@ Where the paper is silent or ambiguous this file takes the following readings:
      floor(t/2), the upper one displaced by ceil(t/2) (Sec. 4.4, the recursive dyadic FHT).
   R9 eq 15 with N - 1 in place of N (k_t = sqrt(1 + m_t^2)); the input rows are physical line
      integrals, the row scale is c_t = k_t * w_t (band-limited ramp at sample spacing 1/k_t).
+  R16 eq 14 in these coordinates: the linogram line (q, t, s) of class q is, in pixel-centre
+     coordinates, x = s + m_t y (q = 0), x = N-1-s - m_t y (q = 1), and the same with x and y
+     swapped (q = 2, 3); the fold s - N is a second line of the same cell.  A parallel-beam
+     sinogram has angle i at theta_i = i pi / P (unit normal (cos, sin)) and detector j at
+     signed distance j - D/2 + 1/2 from the image centre.  A line is looked up by its normal
+     angle in [0, pi) and signed distance, linearly in both (bilinear), zero outside the
+     detector; angle P is angle 0 with the detector mirrored.  Values stay line integrals (no
+     k_t factor: R9 puts it in the row scale).
 
 Parity status: every function here is pinned by the CPU tests (closed forms, library routines,
 brute force, adjoint identities, analytic phantoms); none is "parity unpinned".  The end-to-end
@@ -47,7 +55,7 @@ __all__ = [
     "dyadic_shift", "fht", "fht_T", "to_frame", "from_frame", "fht_forward",
     "fht_backproject", "fbp_fht",
     "fir_ramp_full", "fbp_direct_linogram", "fbp_direct_parallel",
-    "fht_add_count", "relative_rmse",
+    "fht_add_count", "relative_rmse", "linogram_lines", "resample_sinogram",
     "residual_cnn",
 ]
 
@@ -360,6 +368,62 @@ def _lerp_rows(rows: torch.Tensor, pos: torch.Tensor) -> torch.Tensor:
     v0 = torch.where((i0 >= 0) & (i0 < L), v0, torch.zeros_like(v0))
     v1 = torch.where((i1 >= 0) & (i1 < L), v1, torch.zeros_like(v1))
     return v0 * (1 - fr) + v1 * fr
+
+
+def linogram_lines(N: int):
+    """Unit normal (nx, ny) and signed distance rho from the image centre of every linogram
+    line, [2, 4, N, N] each (fold, class q, slope index t, shift s); fold 1 is the line at
+    s - N (reading R16, Sec. 4.1 and eq 14)."""
+    m = slopes(N)[:, None]                                   # [N, 1]
+    k = stretch(N)[:, None]
+    s = torch.arange(N, dtype=DT)[None, :]                   # [1, N]
+    c = (N - 1) / 2.0
+    nx, ny, rho = [], [], []
+    for fold in (0, 1):
+        sf = s - N * fold
+        pos = (sf - c * (1 - m)) / k                         # x_c - m y_c = s
+        neg = (N - 1 - sf - c * (1 + m)) / k                 # x_c + m y_c = N - 1 - s
+        one = torch.ones_like(m) / k
+        nx.append(torch.stack([one, one, -m / k, m / k]).expand(4, N, N))
+        ny.append(torch.stack([-m / k, m / k, one, one]).expand(4, N, N))
+        rho.append(torch.stack([pos.expand(N, N), neg.expand(N, N), pos.expand(N, N),
+                                neg.expand(N, N)]))
+    return torch.stack(nx), torch.stack(ny), torch.stack(rho)
+
+
+def resample_sinogram(sino: torch.Tensor, N: int) -> torch.Tensor:
+    """Linogram [..., 4, N, N] from a parallel-beam sinogram [..., P, D] by bilinear
+    interpolation in (angle, detector) at every linogram line, folds summed (Sec. 4.2, eq 14,
+    reading R16)."""
+    sino = sino.to(DT)
+    Pn, D = sino.shape[-2], sino.shape[-1]
+    nx, ny, rho = linogram_lines(N)
+    phi = torch.atan2(ny, nx)
+    flip = phi < 0
+    phi = torch.where(flip, phi + math.pi, phi)
+    rho = torch.where(flip, -rho, rho)
+    a = phi * (Pn / math.pi)                                 # fractional angle index
+    u = rho + D / 2.0 - 0.5                                  # fractional detector index
+    a0 = torch.floor(a)
+    wa = a - a0
+    a0 = a0.to(torch.int64)
+    flat = sino.reshape(sino.shape[:-2] + (Pn * D,))
+    out = torch.zeros(sino.shape[:-2] + (4, N, N), dtype=DT)
+    for da, w in ((0, 1 - wa), (1, wa)):
+        i = a0 + da
+        wrap = i >= Pn                                       # angle pi = angle 0, mirrored
+        i = torch.where(wrap, i - Pn, i)
+        uu = torch.where(wrap, (D - 1) - u, u)
+        j0 = torch.floor(uu)
+        wu = uu - j0
+        j0 = j0.to(torch.int64)
+        for dj, wj in ((0, 1 - wu), (1, wu)):
+            j = j0 + dj
+            ok = (j >= 0) & (j < D)
+            idx = (i * D + j.clamp(0, D - 1)).reshape(-1)
+            v = flat[..., idx].reshape(sino.shape[:-2] + (2, 4, N, N))
+            out = out + (torch.where(ok, w * wj, torch.zeros_like(wj)) * v).sum(-4)
+    return out
 
 
 def fbp_direct_linogram(P: torch.Tensor, *, chunk_elems: int = 1 << 24) -> torch.Tensor:

@@ -142,6 +142,27 @@ int fbp_direct_filter(const float* sino, float* work, int32_t batch, int32_t n_a
 int fbp_direct_backproject(const float* work, float* img, int32_t batch, int32_t n,
                            int32_t n_angles, int32_t n_det, void* stream);
 
+/* ---- scanner input (Sec. 4.2, eq 14) ----------------------------------------------------- */
+/* Resample a parallel-beam sinogram onto the four linogram line classes.  sino is
+ * [batch][n_angles][n_det] float32: angle i has unit normal (cos, sin) of i * pi / n_angles,
+ * detector j sits at signed distance j - n_det/2 + 1/2 (pixels) from the image centre.  Every
+ * linogram line (class q, slope index t, shift s; the layout above) is looked up by its normal
+ * angle in [0, pi) and its signed distance, linearly in angle and in detector position
+ * (bilinear), zero off the detector; angle pi continues at angle 0 with the detector mirrored.
+ * The two lines of a cell (shift s and its fold s - N) are summed.  Values stay line
+ * integrals: the 1/k_t sample spacing of eq 15 is taken care of by the filter's row scale.
+ * lino is [batch][4][n][n], 16-byte aligned.  n a power of two in [4, 4096], n_angles >= 1,
+ * 1 <= n_det <= 65536, n_angles * n_det <= 2^29, else FBP_EINVAL.  The per-row geometry is built
+ * once per (n, n_angles, n_det, device) in device memory kept until the process ends.  Runs on
+ * `stream`. */
+int fbp_resample_sinogram(const float* sino, float* lino, int32_t batch, int32_t n,
+                          int32_t n_angles, int32_t n_det, void* stream);
+
+/* The method from scanner data: fbp_resample_sinogram into `work` ([batch][4][N][N],
+ * caller-owned scratch, 16-byte aligned), then fbp_reconstruct into img, on the plan's stream. */
+int fbp_reconstruct_sinogram(fbp_plan_t plan, const float* sino, float* work, float* img,
+                             int32_t batch, int32_t n_angles, int32_t n_det);
+
 /* ---- kernel timing -------------------------------------------------------------------- */
 /* Kernel kinds reported by fbp_plan_profile_read. */
 #define FBP_KERNEL_FIRST   0  /* first back-projection pass (with the filter in reconstruct) */

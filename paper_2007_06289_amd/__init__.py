@@ -8,6 +8,7 @@ from .api import (  # noqa: F401
     fbp_plan, fbp_plan_set_coefficients, fbp_filter, fht_backproject, fht_forward,
     fbp_reconstruct, fbp_fit_ramp_iir, fbp_direct_parallel, fbp_direct_filter,
     fbp_direct_backproject, fbp_direct_linogram, fbp_filter_coef_grad, load_library, strerror,
-    fbp_reconstruct_many, fbp_graph_create, Graph,
+    fbp_reconstruct_many, fbp_graph_create, Graph, fbp_resample_sinogram,
+    fbp_reconstruct_sinogram,
 )
 from .autograd import FBPReconstruct, fbp_reconstruct_autograd  # noqa: F401,E402

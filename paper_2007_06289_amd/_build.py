@@ -21,7 +21,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfhtfbp.so")
 
 HIP_SOURCES = ["fht_pass_l4.hip", "fht_pass_l8.hip", "fht_pass_l16.hip", "fht_pass_l32.hip",
-               "fht_pass_l64.hip", "fht_cols.hip", "coef_grad.hip", "conv_net.hip", "direct_fbp.hip",
+               "fht_pass_l64.hip", "fht_cols.hip", "coef_grad.hip", "conv_net.hip", "direct_fbp.hip", "resample.hip",
                "fhtfbp_api.hip"]
 CPP_SOURCES = ["fit_iir.cpp"]
 HIP_FLAGS = [

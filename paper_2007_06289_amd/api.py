@@ -102,6 +102,8 @@ def load_library():
         "fbp_graph_create": ([ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                               ctypes.POINTER(i32), i32, ctypes.POINTER(vp)], ctypes.c_int),
         "fbp_graph_launch": ([vp, vp], ctypes.c_int),
+        "fbp_resample_sinogram": ([vp, vp, i32, i32, i32, i32, vp], ctypes.c_int),
+        "fbp_reconstruct_sinogram": ([vp, vp, vp, vp, i32, i32, i32], ctypes.c_int),
         "fbp_graph_destroy": ([vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
@@ -507,4 +509,36 @@ class Graph:
 
 def fbp_graph_create(plans, linos, imgs) -> Graph:
     return Graph(plans, linos, imgs)
+
+
+def fbp_resample_sinogram(sino: torch.Tensor, n: int, lino: torch.Tensor | None = None):
+    """Parallel-beam sinogram [B, P, D] -> linogram [B, 4, n, n] (bilinear, Sec. 4.2)."""
+    B = _batch_of(sino, 2, "sino")
+    P, D = int(sino.shape[1]), int(sino.shape[2])
+    if lino is None:
+        lino = torch.empty((B, 4, n, n), device=sino.device, dtype=torch.float32)
+    ps = _dev_ptr(sino, "sino", (B, P, D))
+    pl = _dev_ptr(lino, "lino", (B, 4, n, n))
+    _check(load_library().fbp_resample_sinogram(ps, pl, B, int(n), P, D, _stream_ptr()),
+           "fbp_resample_sinogram")
+    return lino
+
+
+def fbp_reconstruct_sinogram(plan: Plan, sino: torch.Tensor, img: torch.Tensor | None = None,
+                             work: torch.Tensor | None = None):
+    """The method from scanner data: resample [B, P, D] onto the linogram, then reconstruct."""
+    B = _batch_of(sino, 2, "sino")
+    P, D = int(sino.shape[1]), int(sino.shape[2])
+    n = plan.n
+    if img is None:
+        img = torch.empty((B, n, n), device=sino.device, dtype=torch.float32)
+    if work is None:
+        work = torch.empty((B, 4, n, n), device=sino.device, dtype=torch.float32)
+    ps = _dev_ptr(sino, "sino", (B, P, D))
+    pw = _dev_ptr(work, "work", (B, 4, n, n))
+    pi = _dev_ptr(img, "img", (B, n, n))
+    plan.bind_stream()
+    _check(load_library().fbp_reconstruct_sinogram(plan.handle, ps, pw, pi, B, P, D),
+           "fbp_reconstruct_sinogram")
+    return img
 

@@ -26,6 +26,11 @@
 #include "fhtfbp_internal.h"
 
 namespace fhtfbp {
+
+// Index of the calling wave in its block, as a wave-uniform (scalar) value: everything derived
+// from it (unit, row pair, relative shift) is then computed once per wave on the scalar unit
+// instead of once per lane.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 namespace {
 
 __device__ __forceinline__ int lds_at(int r, int c, int rs, int log2l) {
@@ -255,9 +260,12 @@ __device__ void filter_tile(const PassArgs& A, float* S, int q, int row0) {
 }
 
 // The same filter for rows stored window-aligned (window position p at LDS column p, skew period
-// 32): every in-chunk access is the chunk's base pointer plus an immediate offset.
+// 32): every in-chunk access is the chunk's base pointer plus an immediate offset.  The caller
+// passes the row factor c_t, and guarantees that all rows of a wave lie in one coefficient
+// group (first_pass_supported): the group's coefficients are then read with scalar loads,
+// which do not wait behind the vector loads of the next tile that are already in flight.
 template <int K>
-__device__ void filter_tile_aligned(const PassArgs& A, float* S, int q, int row0) {
+__device__ void filter_tile_aligned(const PassArgs& A, float* S, int q, int row0, float ct) {
   constexpr int L = 32;
   int tid = threadIdx.x;
   asm volatile("" : "+v"(tid));
@@ -265,16 +273,15 @@ __device__ void filter_tile_aligned(const PassArgs& A, float* S, int q, int row0
   const int r = tid >> A.log2c, c = tid & (C - 1);
   const int N = 1 << A.log2n;
   const int t = row0 + r;
-  const int g = ((q * N + t) * A.groups) / (4 * N);
-  const float* cf = A.coef + (size_t)g * A.coef_stride;
+  const int g = __builtin_amdgcn_readfirstlane(((q * N + t) * A.groups) / (4 * N));
+  cfloat* cf = as_constant(A.coef + (size_t)g * A.coef_stride);
   float bk[K], ak[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     bk[k] = cf[k];
     ak[k] = cf[K + k];
   }
-  const float* phi = cf + 2 * K;
-  const float ct = A.scale[t];
+  cfloat* phi = cf + 2 * K;
   const int base = c * L;
   float* row = S + r * A.rs;
   float* rp = row + base + (base >> 5);       // window positions base .. base + 31
@@ -316,7 +323,7 @@ __device__ void filter_tile_aligned(const PassArgs& A, float* S, int q, int row0
 #pragma unroll
       for (int k = 0; k < K; ++k) u[k] = __shfl_up(tv[k], d, C);
       if (c >= d) {
-        const float* P = phi + j * K * K;
+        cfloat* P = phi + j * K * K;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
           float acc = tv[k];
@@ -374,7 +381,7 @@ __device__ void filter_tile_aligned(const PassArgs& A, float* S, int q, int row0
 #pragma unroll
       for (int k = 0; k < K; ++k) u[k] = __shfl_down(tv[k], d, C);
       if (c + d < C) {
-        const float* P = phi + j * K * K;
+        cfloat* P = phi + j * K * K;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
           float acc = tv[k];
@@ -416,7 +423,7 @@ __device__ void filter_tile_aligned(const PassArgs& A, float* S, int q, int row0
 // barrier, ahead of any write.  Two barriers per level, a handful of registers.
 __device__ __forceinline__ void level_stream(const PassArgs& A, float* S, float* below, int l) {
   const int N = 1 << A.log2n, mask = N - 1;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_id();
   const int waves = blockDim.x >> 6;
   const int log2p = A.log2r - 1;                       // pairs = 2^log2p
   const int segs = waves > (1 << log2p) ? waves >> log2p : 1;
@@ -483,7 +490,7 @@ template <int NBLK>
 __device__ __forceinline__ void level_stream_fast(const PassArgs& A, float* S, float* below,
                                                   int l) {
   const int N = 1 << A.log2n, mask = N - 1;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_id();
   const int waves = blockDim.x >> 6;
   const int log2p = A.log2r - 1;
   const int segs = waves > (1 << log2p) ? waves >> log2p : 1;
@@ -560,12 +567,13 @@ template <int NBLK, bool ROT>
 __device__ __forceinline__ void level_stream_rot(const PassArgs& A, float* S, float* copy, int l,
                                                  int row0) {
   const int N = 1 << A.log2n, mask = N - 1;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_id();
   const int waves = blockDim.x >> 6;
   const int log2p = A.log2r - 1;
-  const int segs = waves > (1 << log2p) ? waves >> log2p : 1;
+  const int log2wv = 31 - __clz(waves);
+  const int log2s = log2wv > log2p ? log2wv - log2p : 0;    // segments per row pair
   constexpr int W = NBLK * 64;
-  const int units = ((1 << log2p) * segs) / waves;
+  const int units = 1 << (log2p + log2s - log2wv);
   auto rel = [&](int pp, int J) -> int {
     int d = -J;
     if constexpr (ROT) {
@@ -579,7 +587,7 @@ __device__ __forceinline__ void level_stream_rot(const PassArgs& A, float* S, fl
   };
   for (int u = 0; u < units; ++u) {
     const int unit = wave + u * waves;
-    const int pair = unit / segs, seg = unit - pair * segs;
+    const int pair = unit >> log2s, seg = unit & ((1 << log2s) - 1);
     const int ib = pair & ((1 << l) - 1), pp = pair >> l;
     const int r1 = ((pp << (l + 1)) | ib) | (1 << l);
     const int d = rel(pp, brev_bits(ib, l));
@@ -590,7 +598,7 @@ __device__ __forceinline__ void level_stream_rot(const PassArgs& A, float* S, fl
   __syncthreads();
   for (int u = 0; u < units; ++u) {
     const int unit = wave + u * waves;
-    const int pair = unit / segs, seg = unit - pair * segs;
+    const int pair = unit >> log2s, seg = unit & ((1 << log2s) - 1);
     const int ib = pair & ((1 << l) - 1), pp = pair >> l;
     const int r0 = (pp << (l + 1)) | ib, r1 = r0 | (1 << l);
     const int d = rel(pp, brev_bits(ib, l));
@@ -886,12 +894,15 @@ __global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
     const int bq = tl / tiles, v = tl - bq * tiles;
     const int q = bq & 3;
     const int row0 = v << F;
+    // N >= 256 here (at least four 64-column blocks per unit), so the 256 consecutive values
+    // of a wave's float4 lie in one row: the row and its window start are wave-uniform
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
       const int e4 = (ltid + k * T) << 2;
-      const int r = e4 >> A.log2n;
+      const int r = __builtin_amdgcn_readfirstlane(e4 >> A.log2n);
       // with the filter, row r is stored window-aligned: shift s at column s - sigma
-      const int x = (e4 - (K > 0 ? window_start_of(row0 + r, A.log2n, A.windowed) : 0)) & mask;
+      const int sg = K > 0 ? window_start_of(row0 + r, A.log2n, A.windowed) : 0;
+      const int x = (e4 - sg) & mask;
       float* d = S + r * A.rs;
       d[x + (x >> 5)] = pre[k].x;
       const int x1 = (x + 1) & mask, x2 = (x + 2) & mask, x3 = (x + 3) & mask;
@@ -900,10 +911,26 @@ __global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
       d[x3 + (x3 >> 5)] = pre[k].w;
     }
     __syncthreads();
-    if constexpr (K > 0) filter_tile_aligned<K>(A, S, q, row0);
-    // the next tile's loads fly during the levels and the write-out of this one
-    asm volatile("" ::: "memory");
+    // the row factor is read before the next tile's loads go out (vector loads complete in
+    // order); those loads then fly during the filter, the levels and the write-out
+    float ct = 0.f;
+    if constexpr (K > 0) {
+      // a wave holds 64 / C consecutive rows (at most 8 here): read their factors with scalar
+      // loads and let each lane pick its row's
+      const int rpw = 64 >> A.log2c;
+      const int wave = __builtin_amdgcn_readfirstlane(ltid >> 6);
+      cfloat* sc = as_constant(A.scale + row0 + wave * rpw);
+      const int lr = (ltid & 63) >> A.log2c;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        if (k < rpw) {
+          const float v = sc[k];
+          ct = (lr == k) ? v : ct;
+        }
+      }
+    }
     if (tl + (int)gridDim.x < A.total_tiles) issue(tl + gridDim.x);
+    if constexpr (K > 0) filter_tile_aligned<K>(A, S, q, row0, ct);
     {
       float* copy = S + (1 << A.log2r) * A.rs;
       for (int l = 0; l < F; ++l) {
@@ -915,17 +942,25 @@ __global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
     float* dst = A.out + (size_t)bq * N * N;
     int stid = tid;
     asm volatile("" : "+v"(stid));
-    for (int e = stid; e < (N << F) >> 2; e += T) {
-      const int rho = (e << 2) >> A.log2n, x = (e << 2) & mask;
+    // as in the deposit, a wave's 256 values lie in one row: row, output row and rotation are
+    // wave-uniform, only the column is per lane
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const int e4 = (stid + k * T) << 2;
+      const int rho = __builtin_amdgcn_readfirstlane(e4 >> A.log2n);
+      const int x = e4 & mask;
       const int i = brev_bits(rho, F);
       const int orow = (i << k_lo) + v;
       const int o = (sig0 + v * i) & mask;
+      const float* srow = S + rho * A.rs;
+      const int p0 = (x - o) & mask, p1 = (x + 1 - o) & mask;
+      const int p2 = (x + 2 - o) & mask, p3 = (x + 3 - o) & mask;
       float4 w;
-      w.x = S[lds_at(rho, (x - o) & mask, A.rs, A.log2l)];
-      w.y = S[lds_at(rho, (x + 1 - o) & mask, A.rs, A.log2l)];
-      w.z = S[lds_at(rho, (x + 2 - o) & mask, A.rs, A.log2l)];
-      w.w = S[lds_at(rho, (x + 3 - o) & mask, A.rs, A.log2l)];
-      *reinterpret_cast<float4*>(dst + (size_t)orow * N + x) = w;
+      w.x = srow[p0 + (p0 >> 5)];
+      w.y = srow[p1 + (p1 >> 5)];
+      w.z = srow[p2 + (p2 >> 5)];
+      w.w = srow[p3 + (p3 >> 5)];
+      *reinterpret_cast<float4*>(dst + orow * N + x) = w;
     }
     __syncthreads();
   }
@@ -939,46 +974,68 @@ __global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
 // one class, rows written with their pending rotation.
 __device__ __forceinline__ int cat(int r, int c, int rs) { return r * rs + c + (c >> 5); }
 
-// Load a tile of 2^log2r rows by 2^log2w + halo columns from each of `ncls` classes (class 0 from
-// c0 starting at column xs0, class 1 from c1 at xs1, cyclically) into skewed LDS rows.  Loads go
-// out in batches, so each thread has up to kColBatch float4 loads in flight before it stores any.
-constexpr int kColBatch = 12;
-__device__ void cols_load_batched(const PassArgs& A, float* S, int rs, int ncls, const float* c0,
-                                  int xs0, const float* c1, int xs1, int row0) {
+// Load a tile of 2^log2r rows by halo + 2^log2w columns from each of NCLS classes into skewed
+// LDS rows (class c at rows c R .. c R + R - 1).  Class c's tile starts at source column
+// col[c] - halo (cyclically: only the halo can wrap, since col[c] + W <= N).  Both parts have
+// power-of-two shapes; each class is read through its own buffer resource, so a load needs
+// one 32-bit offset, and all of a thread's loads of a batch are in flight before it stores.
+// A float4 at a column that is a multiple of 4 never straddles a skew step, so its four LDS
+// words sit at one address plus 0..3.
+template <int NCLS>
+__device__ void cols_load_tile(const PassArgs& A, float* S, int rs, const float* const* cls,
+                               const int* col, int row0) {
   const int N = 1 << A.log2n, mask = N - 1;
   const int R = 1 << A.log2r;
-  const int wt = (1 << A.log2w) + A.halo;
-  const int nv = wt >> 2;                      // float4 per row
-  const int per = R * nv, total = ncls * per;
-  const int T = blockDim.x;
-  for (int base = threadIdx.x; base < total; base += kColBatch * T) {
-    float4 v[kColBatch];
+  const int H = A.halo;
+  const int T = blockDim.x, tid = threadIdx.x;
+  const int lw = A.log2w - 2;                    // log2 of float4 per main row
+  const int lh = 29 - __clz(H);                  // log2(H / 4)
+  __amdgpu_buffer_rsrc_t rsrc[NCLS];
 #pragma unroll
-    for (int k = 0; k < kColBatch; ++k) {
-      const int e = base + k * T;
-      if (e < total) {
-        const int cl = e >= per ? 1 : 0;
-        const int ee = e - cl * per;
-        const int r = ee / nv, c4 = (ee - r * nv) << 2;
-        const float* src = cl ? c1 : c0;
-        const int xs = cl ? xs1 : xs0;
-        v[k] = *reinterpret_cast<const float4*>(src + (size_t)(row0 + r) * N + ((xs + c4) & mask));
-      }
-    }
+  for (int c = 0; c < NCLS; ++c)
+    rsrc[c] = __builtin_amdgcn_make_buffer_rsrc((void*)cls[c], (short)0, N * N * 4, kBufferDword3);
+  auto put = [&](int c, int r, int lc, const u32x4& w) {
+    float* d = S + (c * R + r) * rs + lc + (lc >> 5);
+    d[0] = __uint_as_float(w.x);
+    d[1] = __uint_as_float(w.y);
+    d[2] = __uint_as_float(w.z);
+    d[3] = __uint_as_float(w.w);
+  };
+  // main part: columns H .. H + W - 1 of the tile
+  constexpr int B = 4;
+  const int per = R << lw;
+  for (int base = tid; base < per; base += B * T) {
+    u32x4 v[NCLS][B];
 #pragma unroll
-    for (int k = 0; k < kColBatch; ++k) {
-      const int e = base + k * T;
-      if (e < total) {
-        const int cl = e >= per ? 1 : 0;
-        const int ee = e - cl * per;
-        const int r = ee / nv, c4 = (ee - r * nv) << 2;
-        float* d = S + (cl * R + r) * rs;
-        d[c4 + (c4 >> 5)] = v[k].x;
-        d[c4 + 1 + ((c4 + 1) >> 5)] = v[k].y;
-        d[c4 + 2 + ((c4 + 2) >> 5)] = v[k].z;
-        d[c4 + 3 + ((c4 + 3) >> 5)] = v[k].w;
+    for (int c = 0; c < NCLS; ++c)
+#pragma unroll
+      for (int k = 0; k < B; ++k) {
+        const int e = base + k * T;
+        if (e < per) {
+          const int r = e >> lw, j = e & ((1 << lw) - 1);
+          v[c][k] = __builtin_amdgcn_raw_buffer_load_b128(
+              rsrc[c], ((row0 + r) * N + col[c] + 4 * j) * 4, 0, 0);
+        }
       }
-    }
+#pragma unroll
+    for (int c = 0; c < NCLS; ++c)
+#pragma unroll
+      for (int k = 0; k < B; ++k) {
+        const int e = base + k * T;
+        if (e < per) put(c, e >> lw, H + 4 * (e & ((1 << lw) - 1)), v[c][k]);
+      }
+  }
+  // halo: columns 0 .. H - 1 of the tile, source columns col[c] - H .. col[c] - 1 cyclically
+  const int perh = R << lh;
+  for (int e = tid; e < perh; e += T) {
+    const int r = e >> lh, j = e & ((1 << lh) - 1);
+    u32x4 v[NCLS];
+#pragma unroll
+    for (int c = 0; c < NCLS; ++c)
+      v[c] = __builtin_amdgcn_raw_buffer_load_b128(
+          rsrc[c], ((row0 + r) * N + ((col[c] - H + 4 * j) & mask)) * 4, 0, 0);
+#pragma unroll
+    for (int c = 0; c < NCLS; ++c) put(c, r, 4 * j, v[c]);
   }
 }
 
@@ -986,7 +1043,7 @@ __device__ void cols_load_batched(const PassArgs& A, float* S, int rs, int ncls,
 // top in batches of four 64-column blocks (reads before writes).  Columns below J + 1 are left
 // as they are (they only feed outputs below the halo).
 __device__ void cols_level(float* S, int rs, int log2r, int ncls, int wt, int l) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_id(), waves = blockDim.x >> 6;
   const int pairs = 1 << (log2r - 1);
   const int units = ncls * pairs;
   const int R = 1 << log2r;
@@ -1027,7 +1084,7 @@ __device__ void cols_level(float* S, int rs, int log2r, int ncls, int wt, int l)
 // bb >= 1 covers columns 64 bb - pad + lane, all of them >= J + 1; block 0 is masked.
 template <int NBLK>
 __device__ void cols_level_fast(float* S, int rs, int log2r, int ncls, int pad, int l) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_id(), waves = blockDim.x >> 6;
   const int pairs = 1 << (log2r - 1);
   const int units = ncls * pairs;
   const int R = 1 << log2r;
@@ -1101,7 +1158,11 @@ __global__ void __launch_bounds__(512) fht_cols_kernel(PassArgs A) {
     const bool hpass = A.out_mode == OUT_IMG_H;
     const bool vec = R >= 4;                      // float4 image access along i (H) or u (V)
     const int n4 = (R * W) >> 2;
-    cols_load_batched(A, S, rs, 2, c0, (cx - H) & mask, c1, (N - cx - W - H) & mask, row0);
+    {
+      const float* cl[2] = {c0, c1};
+      const int cc[2] = {cx, N - cx - W};
+      cols_load_tile<2>(A, S, rs, cl, cc, row0);
+    }
     // the H pass adds into image values that do not depend on the levels: load them now
     constexpr int kOld = 8;
     float4 old[kOld];
@@ -1183,7 +1244,11 @@ __global__ void __launch_bounds__(512) fht_cols_kernel(PassArgs A) {
     const int row0 = (j << A.k_hi) + (v << F);
     const int k_lo = A.k_hi - F;
     const float* cls = A.in + (size_t)bq * N * N;
-    cols_load_batched(A, S, rs, 1, cls, (cx - H) & mask, cls, 0, row0);
+    {
+      const float* cl[1] = {cls};
+      const int cc[1] = {cx};
+      cols_load_tile<1>(A, S, rs, cl, cc, row0);
+    }
     __syncthreads();
     const int pad = 64 * ((wt + 63) >> 6) - wt;
     for (int l = 0; l < F; ++l) {

@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <deque>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -358,6 +359,11 @@ bool first_pass_supported(const PassArgs& a) {
   const int waves = threads >> 6, pairs = 1 << (a.log2r - 1);
   const int segs = waves > pairs ? waves / pairs : 1;
   const int nblk = ((1 << a.log2n) / segs) >> 6;
+  // the filter reads a wave's coefficients once for all its rows: the rows of a wave
+  // (64 / C of them) must lie in one angle group (4N / groups consecutive rows)
+  const int rows_per_wave = 64 >> a.log2c;
+  const int rows_per_group = (4 << a.log2n) / std::max(1, a.groups);
+  if (a.order > 0 && (rows_per_wave < 1 || rows_per_group % rows_per_wave != 0)) return false;
   return nblk == 4 || nblk == 8 || nblk == 16;
 }
 
@@ -397,7 +403,7 @@ struct DirectTables {
   float* w = nullptr;     // [rows] row weight (linogram only)
 };
 std::mutex g_tables_mu;
-std::vector<DirectTables> g_tables;
+std::deque<DirectTables> g_tables;   // a deque keeps earlier entries in place as it grows
 
 const DirectTables* direct_tables(int kind, int n, int rows, int ndet) {
   int dev = 0;
@@ -456,6 +462,78 @@ const DirectTables* direct_tables(int kind, int n, int rows, int ndet) {
   }
   g_tables.push_back(t);
   return &g_tables.back();
+}
+
+// Per-row geometry of the sinogram resampling (Sec. 4.2, eq 14), one table per (N, P, D,
+// device), kept for the life of the process.
+struct ResampleTables {
+  int n, angles, ndet, device;
+  ResampleRow* rows = nullptr;
+};
+std::deque<ResampleTables> g_resample;
+
+const ResampleTables* resample_tables(int n, int P, int D) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lock(g_tables_mu);
+  for (auto& t : g_resample)
+    if (t.n == n && t.angles == P && t.ndet == D && t.device == dev) return &t;
+  const int N = n;
+  const double pi = 3.14159265358979323846;
+  const double c = 0.5 * (N - 1);
+  std::vector<ResampleRow> rows(4 * N);
+  for (int q = 0; q < 4; ++q)
+    for (int tt = 0; tt < N; ++tt) {
+      const double m = N > 1 ? (double)tt / (N - 1) : 0.0;
+      const double k = sqrt(1.0 + m * m);
+      // class lines in pixel-centre coordinates: x = s + m y (q = 0), x = N-1-s - m y (q = 1),
+      // x and y swapped for q = 2, 3; normal (nx, ny), signed distance alpha + beta s from the
+      // image centre
+      double nx, ny, alpha, beta;
+      if (q == 0 || q == 2) {
+        alpha = -c * (1.0 - m) / k;
+        beta = 1.0 / k;
+      } else {
+        alpha = (N - 1 - c * (1.0 + m)) / k;
+        beta = -1.0 / k;
+      }
+      if (q == 0) { nx = 1.0 / k; ny = -m / k; }
+      else if (q == 1) { nx = 1.0 / k; ny = m / k; }
+      else if (q == 2) { nx = -m / k; ny = 1.0 / k; }
+      else { nx = m / k; ny = 1.0 / k; }
+      double phi = atan2(ny, nx);
+      if (phi < 0) {   // normal angle into [0, pi): flip the normal and the distance
+        phi += pi;
+        alpha = -alpha;
+        beta = -beta;
+      }
+      const double a = phi * P / pi;
+      int a0 = (int)floor(a);
+      double wa = a - a0;
+      if (a0 >= P) {
+        a0 = P - 1;
+        wa = 1.0;
+      }
+      ResampleRow r;
+      r.a0 = a0;
+      r.a1 = a0 + 1 < P ? a0 + 1 : 0;
+      r.wrap = a0 + 1 < P ? 0 : 1;
+      r.wa = (float)wa;
+      r.u0 = (float)(alpha + 0.5 * D - 0.5);
+      r.u1 = (float)(alpha - beta * N + 0.5 * D - 0.5);
+      r.du = (float)beta;
+      r.pad = 0.f;
+      rows[q * N + tt] = r;
+    }
+  ResampleTables t{n, P, D, dev};
+  if (hipMalloc(&t.rows, rows.size() * sizeof(ResampleRow)) != hipSuccess) return nullptr;
+  if (hipMemcpy(t.rows, rows.data(), rows.size() * sizeof(ResampleRow),
+                hipMemcpyHostToDevice) != hipSuccess) {
+    hipFree(t.rows);
+    return nullptr;
+  }
+  g_resample.push_back(t);
+  return &g_resample.back();
 }
 
 }  // namespace
@@ -822,6 +900,32 @@ int fbp_cnn_wgrad(int32_t cin, int32_t cout, const float* dz32, const uint16_t* 
                           (hipStream_t)stream) == hipSuccess
              ? FBP_OK
              : FBP_EDEVICE;
+}
+
+int fbp_resample_sinogram(const float* sino, float* lino, int32_t batch, int32_t n,
+                          int32_t n_angles, int32_t n_det, void* stream) {
+  if (batch < 0 || !is_pow2(n) || n < 4 || n > 4096 || n_angles < 1 || n_det < 1 ||
+      n_det > (1 << 16) || (int64_t)n_angles * n_det > (1ll << 31) / 4)
+    return FBP_EINVAL;
+  if (batch == 0) return FBP_OK;
+  if (!sino || !lino || !aligned16(lino)) return FBP_EINVAL;
+  const ResampleTables* t = resample_tables(n, n_angles, n_det);
+  if (!t) return FBP_ENOMEM;
+  return launch_resample(sino, lino, t->rows, batch, n, n_angles, n_det, (hipStream_t)stream) ==
+                 hipSuccess
+             ? FBP_OK
+             : FBP_EDEVICE;
+}
+
+int fbp_reconstruct_sinogram(fbp_plan_t p, const float* sino, float* work, float* img,
+                             int32_t batch, int32_t n_angles, int32_t n_det) {
+  int rc = check_batch(p, batch);
+  if (rc != FBP_OK) return rc;
+  if (batch == 0) return FBP_OK;
+  if (!work || !img || !aligned16(work) || !aligned16(img)) return FBP_EINVAL;
+  rc = fbp_resample_sinogram(sino, work, batch, p->n, n_angles, n_det, p->stream);
+  if (rc != FBP_OK) return rc;
+  return run_passes(p, work, img, batch, false, true, plan_issue(p));
 }
 
 int fbp_direct_linogram(const float* lino, float* work, float* img, int32_t batch, int32_t n,

@@ -54,6 +54,11 @@ struct PassArgs {
 constexpr int kBufferDword3 = 0x00020000;
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
+// Tables that stay constant for a whole launch (coefficients, row factors), read through the
+// constant address space so that wave-uniform reads become scalar loads.
+typedef const __attribute__((address_space(4))) float cfloat;
+__device__ inline cfloat* as_constant(const float* p) { return (cfloat*)(uintptr_t)p; }
+
 // Window start of row t (the same values as the `sigma` table): the window is centred on
 // floor((N-1-t)/2), the intercept of the row's central line, and begins N/2 shifts below it.
 __host__ __device__ inline int window_start_of(int t, int log2n, int windowed) {
@@ -109,6 +114,17 @@ inline size_t cols_lds_bytes(const PassArgs& a) {
   return (size_t)cols_classes(a) * (1 << a.log2r) * cols_rs(a) * sizeof(float);
 }
 inline int cols_threads(const PassArgs& a) { return cols_classes(a) == 2 ? 512 : 256; }
+
+// Sinogram-to-linogram resampling: per linogram row (class q, slope t), the two sinogram
+// angles it lies between (a1 = a0 + 1, or 0 when a0 + 1 = P with the detector mirrored: wrap),
+// the weight of a1, and the detector position u = u0 + du * s of the line at shift s, and
+// u = u1 + du * s of its fold at s - N (both bases computed in double).
+struct ResampleRow {
+  int a0, a1, wrap;
+  float wa, u0, u1, du, pad;
+};
+hipError_t launch_resample(const float* sino, float* lino, const ResampleRow* tab, int batch,
+                           int N, int P, int D, hipStream_t stream);
 
 // Coefficient gradient of the recursive pair (writes out[groups][2][K0]).
 hipError_t launch_coef_grad(const PassArgs& a, const float* g, double* partial, double* out,

@@ -228,3 +228,36 @@ def relative_rmse(model_or_plan, lino: torch.Tensor, target: torch.Tensor, mask:
         num += float((d * d).sum())
         den += float((target[i:i + chunk][:, mask].double() ** 2).sum())
     return math.sqrt(num / den)
+
+
+def load_model(path: str, n: int, max_batch: int) -> LearnedFBP:
+    """A LearnedFBP restored from ``save`` output (tensors only, no code is unpickled)."""
+    d = torch.load(path, map_location="cpu", weights_only=True)
+    if int(d["n"]) != n:
+        raise ValueError(f"model at {path} is for N={int(d['n'])}, not {n}")
+    m = LearnedFBP(n, max_batch, order=int(d["order"]), groups=int(d["groups"]),
+                   cnn="cnn" in d)
+    m.load_state_dict(d)
+    b, a = m.coefficients()
+    api.fbp_plan_set_coefficients(m.plan, b.detach().numpy(), a.detach().numpy())
+    return m
+
+
+def reconstructor(n: int, max_batch: int, path: str | None = None, order: int = 4):
+    """lino [B,4,N,N] -> img [B,N,N]: the learned model saved at ``path`` when there is one for
+    this N, else the plain FHT-FBP with an order-``order`` pair fitted to the ramp (the
+    fallback).  Returns (callable, "learned" | "plain")."""
+    import os
+    if path and os.path.exists(path):
+        try:
+            m = load_model(path, n, max_batch)
+        except (ValueError, KeyError, RuntimeError):
+            m = None
+        if m is not None:
+            def run(lino):
+                with torch.no_grad():
+                    return m(lino)
+            return run, "learned"
+    b, a, _ = api.fbp_fit_ramp_iir(order, min(n, 512), dc_zero=order > 1)
+    plan = api.fbp_plan(n, max_batch, b, a)
+    return (lambda lino: api.fbp_reconstruct(plan, lino)), "plain"

@@ -129,3 +129,31 @@ def test_learned_filter_lowers_error_against_direct_fbp(gpu_lib):
     plain.close()
     model.close()
     assert e_l < 0.8 * e_p
+
+
+def test_saved_model_round_trip_and_plain_fallback(gpu_lib, tmp_path):
+    import paper_2007_06289_amd.learned as L
+    api = gpu_lib
+    N = 64
+    lino = I.linogram(I.random_ellipses(N, 6, seed=12, batch=2), N, device="cuda",
+                      dtype=torch.float32)
+    model = L.LearnedFBP(N, 2, order=4, groups=8, cnn=True, seed=3)
+    with torch.no_grad():
+        model.theta.add_(0.05)                     # move away from the fitted start
+        model.cnn["b3"].add_(0.01)
+        want = model(lino)
+    path = str(tmp_path / "model.pt")
+    model.save(path)
+    run, kind = L.reconstructor(N, 2, path)
+    assert kind == "learned"
+    assert torch.allclose(run(lino), want, rtol=0, atol=0)
+    # no model, or a model for another size: the plain FHT-FBP with fitted coefficients
+    run, kind = L.reconstructor(N, 2, str(tmp_path / "missing.pt"))
+    b, a, _ = api.fbp_fit_ramp_iir(4, N, dc_zero=True)
+    with api.fbp_plan(N, 2, b, a) as plain:
+        ref = api.fbp_reconstruct(plain, lino)
+        assert kind == "plain" and torch.equal(run(lino), ref)
+        run, kind = L.reconstructor(N * 2, 2, path)
+        assert kind == "plain"
+    torch.cuda.synchronize()
+    model.close()

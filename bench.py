@@ -47,7 +47,7 @@ def parse():
                     help="search the pass schedule first (cached per device and shape)")
     ap.add_argument("--rocprof-summary", metavar="DIR",
                     help="summarise rocprofv3 csv output under DIR (subfolders trace, fetch, "
-                         "write, copyf, copyw, sq) as text for the profiles folder, and exit")
+                         "write, copyf, copyw, sq, sq2) as text for the profiles folder, and exit")
     ap.add_argument("--profile", default=None,
                     help="profile summary whose HBM counters fill roofline.traffic when its "
                          "kernel-source hash matches (default: the one for this workload)")
@@ -180,7 +180,7 @@ def rocprof_summary(d: str, n: int, batch: int, order: int) -> str:
                              f"{kv['write_size_bytes'] / 1e9:8.3f} GB  total {t / 1e9:8.3f} GB  "
                              f"algorithmic {a / 1e9:8.3f} GB  ratio {t / a if a else 0:6.3f}")
     sq = defaultdict(lambda: defaultdict(list))
-    for r in rows("sq/*counter_collection.csv"):
+    for r in rows("sq/*counter_collection.csv") + rows("sq2/*counter_collection.csv"):
         k = _kind(r["Kernel_Name"])
         if k:
             sq[k][r["Counter_Name"]].append(float(r["Counter_Value"]))

@@ -124,129 +124,115 @@ __device__ void filter_tile(const PassArgs& A, float* S, int q, int row0) {
     return (i >= 0 && i < N) ? v : 0.f;
   };
 
+  // Same arithmetic, in the same order, as filter_tile_aligned: one step of the causal and one
+  // of the anticausal half per iteration (two independent dependency chains), then both carry
+  // scans, then both carry corrections.  Step s handles causal sample s and anticausal sample
+  // L - 1 - s; a sample's first contribution assigns y, the second adds.
   float y[L];
-  float st[K], xs[K];   // recursion state (y[i-1], ...), input window (x[i], x[i-1], ...)
-  // causal pass, zero entering state
-  asm volatile("" : "+v"(sig));
-  // each step shifts the window up by one and puts the new sample in xs[0], so xs[m] starts as
-  // the sample m + 1 positions before the chunk
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    st[k] = 0.f;
-    xs[k] = (k < K - 1) ? at(base - 1 - k) : 0.f;
-  }
-#pragma unroll
-  for (int i = 0; i < L; ++i) {
-#pragma unroll
-    for (int k = K - 1; k > 0; --k) xs[k] = xs[k - 1];
-    xs[0] = in(base + i);
-    float acc = 0.f;
-#pragma unroll
-    for (int k = 0; k < K; ++k) acc = fmaf(bk[k], xs[k], acc);
-#pragma unroll
-    for (int k = 0; k < K; ++k) acc = fmaf(-ak[k], st[k], acc);
-    y[i] = acc;
-#pragma unroll
-    for (int k = K - 1; k > 0; --k) st[k] = st[k - 1];
-    st[0] = acc;
-  }
-  // inclusive scan of the end states over the chunks to the left, then the response of the
-  // recursion to the entering state
-  {
-    float tv[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) tv[k] = st[k];
-    for (int j = 0; (1 << j) < C; ++j) {
-      const int d = 1 << j;
-      float u[K];
-#pragma unroll
-      for (int k = 0; k < K; ++k) u[k] = __shfl_up(tv[k], d, C);
-      if (c >= d) {
-        const float* P = phi + j * K * K;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          float acc = tv[k];
-#pragma unroll
-          for (int m = 0; m < K; ++m) acc = fmaf(P[k * K + m], u[m], acc);
-          tv[k] = acc;
-        }
-      }
-    }
-    // every lane takes part in the shuffle (a lane reading an inactive lane gets nothing)
-#pragma unroll
-    for (int k = 0; k < K; ++k) st[k] = (C > 1) ? __shfl_up(tv[k], 1, C) : 0.f;
-    if (c == 0) {
-#pragma unroll
-      for (int k = 0; k < K; ++k) st[k] = 0.f;
-    }
-#pragma unroll
-    for (int i = 0; i < L; ++i) {
-      float z = 0.f;
-#pragma unroll
-      for (int k = 0; k < K; ++k) z = fmaf(-ak[k], st[k], z);
-      y[i] += z;
-#pragma unroll
-      for (int k = K - 1; k > 0; --k) st[k] = st[k - 1];
-      st[0] = z;
-    }
-  }
-  // anticausal pass, zero entering state, added into y as it goes
+  float stc[K], sta[K], xc[K], xa[K];
   asm volatile("" : "+v"(sig));
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    st[k] = 0.f;
-    xs[k] = (k < K - 1) ? at(base + L + k) : 0.f;
+    stc[k] = 0.f;
+    sta[k] = 0.f;
+    xc[k] = (k < K - 1) ? at(base - 1 - k) : 0.f;
+    xa[k] = (k < K - 1) ? at(base + L + k) : 0.f;
   }
 #pragma unroll
-  for (int i = L - 1; i >= 0; --i) {
+  for (int s = 0; s < L; ++s) {
+    const int i = s, j = L - 1 - s;
 #pragma unroll
-    for (int k = K - 1; k > 0; --k) xs[k] = xs[k - 1];
-    xs[0] = in(base + i);
-    float acc = 0.f;
+    for (int k = K - 1; k > 0; --k) {
+      xc[k] = xc[k - 1];
+      xa[k] = xa[k - 1];
+    }
+    xc[0] = in(base + i);
+    xa[0] = in(base + j);
+    float ac = 0.f, aa = 0.f;
 #pragma unroll
-    for (int k = 0; k < K; ++k) acc = fmaf(bk[k], xs[k], acc);
+    for (int k = 0; k < K; ++k) {
+      ac = fmaf(bk[k], xc[k], ac);
+      aa = fmaf(bk[k], xa[k], aa);
+    }
 #pragma unroll
-    for (int k = 0; k < K; ++k) acc = fmaf(-ak[k], st[k], acc);
-    y[i] += acc;
+    for (int k = 0; k < K; ++k) {
+      ac = fmaf(-ak[k], stc[k], ac);
+      aa = fmaf(-ak[k], sta[k], aa);
+    }
+    if (s < L / 2) {
+      y[i] = ac;
+      y[j] = aa;
+    } else {
+      y[i] += ac;
+      y[j] += aa;
+    }
 #pragma unroll
-    for (int k = K - 1; k > 0; --k) st[k] = st[k - 1];
-    st[0] = acc;
+    for (int k = K - 1; k > 0; --k) {
+      stc[k] = stc[k - 1];
+      sta[k] = sta[k - 1];
+    }
+    stc[0] = ac;
+    sta[0] = aa;
   }
   {
-    float tv[K];
+    float tc[K], ta[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) tv[k] = st[k];
-    for (int j = 0; (1 << j) < C; ++j) {
-      const int d = 1 << j;
-      float u[K];
+    for (int k = 0; k < K; ++k) {
+      tc[k] = stc[k];
+      ta[k] = sta[k];
+    }
+    for (int jj = 0; (1 << jj) < C; ++jj) {
+      const int d = 1 << jj;
+      float uc[K], ua[K];
 #pragma unroll
-      for (int k = 0; k < K; ++k) u[k] = __shfl_down(tv[k], d, C);
-      if (c + d < C) {
-        const float* P = phi + j * K * K;
+      for (int k = 0; k < K; ++k) {
+        uc[k] = __shfl_up(tc[k], d, C);
+        ua[k] = __shfl_down(ta[k], d, C);
+      }
+      const float* P = phi + jj * K * K;
+      float nc[K], na[K];
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-          float acc = tv[k];
+      for (int k = 0; k < K; ++k) {
+        float accc = tc[k], acca = ta[k];
 #pragma unroll
-          for (int m = 0; m < K; ++m) acc = fmaf(P[k * K + m], u[m], acc);
-          tv[k] = acc;
+        for (int m = 0; m < K; ++m) {
+          accc = fmaf(P[k * K + m], uc[m], accc);
+          acca = fmaf(P[k * K + m], ua[m], acca);
         }
+        nc[k] = accc;
+        na[k] = acca;
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        tc[k] = (c >= d) ? nc[k] : tc[k];
+        ta[k] = (c + d < C) ? na[k] : ta[k];
       }
     }
 #pragma unroll
-    for (int k = 0; k < K; ++k) st[k] = (C > 1) ? __shfl_down(tv[k], 1, C) : 0.f;
-    if (c == C - 1) {
-#pragma unroll
-      for (int k = 0; k < K; ++k) st[k] = 0.f;
+    for (int k = 0; k < K; ++k) {
+      const float pc = (C > 1) ? __shfl_up(tc[k], 1, C) : 0.f;
+      const float pa = (C > 1) ? __shfl_down(ta[k], 1, C) : 0.f;
+      stc[k] = (c == 0) ? 0.f : pc;
+      sta[k] = (c == C - 1) ? 0.f : pa;
     }
 #pragma unroll
-    for (int i = L - 1; i >= 0; --i) {
-      float z = 0.f;
+    for (int s = 0; s < L; ++s) {
+      const int i = s, j = L - 1 - s;
+      float zc = 0.f, za = 0.f;
 #pragma unroll
-      for (int k = 0; k < K; ++k) z = fmaf(-ak[k], st[k], z);
-      y[i] += z;
+      for (int k = 0; k < K; ++k) {
+        zc = fmaf(-ak[k], stc[k], zc);
+        za = fmaf(-ak[k], sta[k], za);
+      }
+      y[i] += zc;
+      y[j] += za;
 #pragma unroll
-      for (int k = K - 1; k > 0; --k) st[k] = st[k - 1];
-      st[0] = z;
+      for (int k = K - 1; k > 0; --k) {
+        stc[k] = stc[k - 1];
+        sta[k] = sta[k - 1];
+      }
+      stc[0] = zc;
+      sta[0] = za;
     }
   }
   __syncthreads();   // every chunk has read its samples and its neighbours' halo
@@ -290,122 +276,117 @@ __device__ void filter_tile_aligned(const PassArgs& A, float* S, int q, int row0
     const float v = row[pc + (pc >> 5)];
     return (p >= 0 && p < N) ? v : 0.f;
   };
+  // The causal and the anticausal halves are independent until their sum, and so are their
+  // carry scans and carry corrections: each loop below runs one step of both, two independent
+  // dependency chains.  Step s handles causal sample s and anticausal sample L - 1 - s; a
+  // sample's first contribution assigns y, the second adds.
   float y[L];
-  float st[K], xs[K];
+  float stc[K], sta[K], xc[K], xa[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    st[k] = 0.f;
-    xs[k] = (k < K - 1) ? at(base - 1 - k) : 0.f;
+    stc[k] = 0.f;
+    sta[k] = 0.f;
+    xc[k] = (k < K - 1) ? at(base - 1 - k) : 0.f;
+    xa[k] = (k < K - 1) ? at(base + L + k) : 0.f;
   }
 #pragma unroll
-  for (int i = 0; i < L; ++i) {
+  for (int s = 0; s < L; ++s) {
+    const int i = s, j = L - 1 - s;
 #pragma unroll
-    for (int k = K - 1; k > 0; --k) xs[k] = xs[k - 1];
-    if ((i & 7) == 0) asm volatile("" ::: "memory");   // keeps at most 8 LDS reads in flight
-    xs[0] = rp[i];
-    float acc = 0.f;
+    for (int k = K - 1; k > 0; --k) {
+      xc[k] = xc[k - 1];
+      xa[k] = xa[k - 1];
+    }
+    if ((s & 3) == 0) asm volatile("" ::: "memory");   // keeps at most 8 LDS reads in flight
+    xc[0] = rp[i];
+    xa[0] = rp[j];
+    float ac = 0.f, aa = 0.f;
 #pragma unroll
-    for (int k = 0; k < K; ++k) acc = fmaf(bk[k], xs[k], acc);
+    for (int k = 0; k < K; ++k) {
+      ac = fmaf(bk[k], xc[k], ac);
+      aa = fmaf(bk[k], xa[k], aa);
+    }
 #pragma unroll
-    for (int k = 0; k < K; ++k) acc = fmaf(-ak[k], st[k], acc);
-    y[i] = acc;
+    for (int k = 0; k < K; ++k) {
+      ac = fmaf(-ak[k], stc[k], ac);
+      aa = fmaf(-ak[k], sta[k], aa);
+    }
+    if (s < L / 2) {
+      y[i] = ac;
+      y[j] = aa;
+    } else {
+      y[i] += ac;
+      y[j] += aa;
+    }
 #pragma unroll
-    for (int k = K - 1; k > 0; --k) st[k] = st[k - 1];
-    st[0] = acc;
+    for (int k = K - 1; k > 0; --k) {
+      stc[k] = stc[k - 1];
+      sta[k] = sta[k - 1];
+    }
+    stc[0] = ac;
+    sta[0] = aa;
   }
   {
-    float tv[K];
+    // chunk end states through Phi_j: causal from the chunks on the left, anticausal from the
+    // right (Hillis-Steele; every lane takes part in every shuffle)
+    float tc[K], ta[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) tv[k] = st[k];
-    for (int j = 0; (1 << j) < C; ++j) {
-      const int d = 1 << j;
-      float u[K];
+    for (int k = 0; k < K; ++k) {
+      tc[k] = stc[k];
+      ta[k] = sta[k];
+    }
+    for (int jj = 0; (1 << jj) < C; ++jj) {
+      const int d = 1 << jj;
+      float uc[K], ua[K];
 #pragma unroll
-      for (int k = 0; k < K; ++k) u[k] = __shfl_up(tv[k], d, C);
-      if (c >= d) {
-        cfloat* P = phi + j * K * K;
+      for (int k = 0; k < K; ++k) {
+        uc[k] = __shfl_up(tc[k], d, C);
+        ua[k] = __shfl_down(ta[k], d, C);
+      }
+      cfloat* P = phi + jj * K * K;
+      float nc[K], na[K];
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-          float acc = tv[k];
+      for (int k = 0; k < K; ++k) {
+        float accc = tc[k], acca = ta[k];
 #pragma unroll
-          for (int m = 0; m < K; ++m) acc = fmaf(P[k * K + m], u[m], acc);
-          tv[k] = acc;
+        for (int m = 0; m < K; ++m) {
+          accc = fmaf(P[k * K + m], uc[m], accc);
+          acca = fmaf(P[k * K + m], ua[m], acca);
         }
+        nc[k] = accc;
+        na[k] = acca;
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        tc[k] = (c >= d) ? nc[k] : tc[k];
+        ta[k] = (c + d < C) ? na[k] : ta[k];
       }
     }
 #pragma unroll
-    for (int k = 0; k < K; ++k) st[k] = (C > 1) ? __shfl_up(tv[k], 1, C) : 0.f;
-    if (c == 0) {
-#pragma unroll
-      for (int k = 0; k < K; ++k) st[k] = 0.f;
+    for (int k = 0; k < K; ++k) {
+      const float pc = (C > 1) ? __shfl_up(tc[k], 1, C) : 0.f;
+      const float pa = (C > 1) ? __shfl_down(ta[k], 1, C) : 0.f;
+      stc[k] = (c == 0) ? 0.f : pc;
+      sta[k] = (c == C - 1) ? 0.f : pa;
     }
 #pragma unroll
-    for (int i = 0; i < L; ++i) {
-      float z = 0.f;
+    for (int s = 0; s < L; ++s) {
+      const int i = s, j = L - 1 - s;
+      float zc = 0.f, za = 0.f;
 #pragma unroll
-      for (int k = 0; k < K; ++k) z = fmaf(-ak[k], st[k], z);
-      y[i] += z;
-#pragma unroll
-      for (int k = K - 1; k > 0; --k) st[k] = st[k - 1];
-      st[0] = z;
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    st[k] = 0.f;
-    xs[k] = (k < K - 1) ? at(base + L + k) : 0.f;
-  }
-#pragma unroll
-  for (int i = L - 1; i >= 0; --i) {
-#pragma unroll
-    for (int k = K - 1; k > 0; --k) xs[k] = xs[k - 1];
-    if ((i & 7) == 0) asm volatile("" ::: "memory");   // keeps at most 8 LDS reads in flight
-    xs[0] = rp[i];
-    float acc = 0.f;
-#pragma unroll
-    for (int k = 0; k < K; ++k) acc = fmaf(bk[k], xs[k], acc);
-#pragma unroll
-    for (int k = 0; k < K; ++k) acc = fmaf(-ak[k], st[k], acc);
-    y[i] += acc;
-#pragma unroll
-    for (int k = K - 1; k > 0; --k) st[k] = st[k - 1];
-    st[0] = acc;
-  }
-  {
-    float tv[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) tv[k] = st[k];
-    for (int j = 0; (1 << j) < C; ++j) {
-      const int d = 1 << j;
-      float u[K];
-#pragma unroll
-      for (int k = 0; k < K; ++k) u[k] = __shfl_down(tv[k], d, C);
-      if (c + d < C) {
-        cfloat* P = phi + j * K * K;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          float acc = tv[k];
-#pragma unroll
-          for (int m = 0; m < K; ++m) acc = fmaf(P[k * K + m], u[m], acc);
-          tv[k] = acc;
-        }
+      for (int k = 0; k < K; ++k) {
+        zc = fmaf(-ak[k], stc[k], zc);
+        za = fmaf(-ak[k], sta[k], za);
       }
-    }
+      y[i] += zc;
+      y[j] += za;
 #pragma unroll
-    for (int k = 0; k < K; ++k) st[k] = (C > 1) ? __shfl_down(tv[k], 1, C) : 0.f;
-    if (c == C - 1) {
-#pragma unroll
-      for (int k = 0; k < K; ++k) st[k] = 0.f;
-    }
-#pragma unroll
-    for (int i = L - 1; i >= 0; --i) {
-      float z = 0.f;
-#pragma unroll
-      for (int k = 0; k < K; ++k) z = fmaf(-ak[k], st[k], z);
-      y[i] += z;
-#pragma unroll
-      for (int k = K - 1; k > 0; --k) st[k] = st[k - 1];
-      st[0] = z;
+      for (int k = K - 1; k > 0; --k) {
+        stc[k] = stc[k - 1];
+        sta[k] = sta[k - 1];
+      }
+      stc[0] = zc;
+      sta[0] = za;
     }
   }
   __syncthreads();
@@ -595,7 +576,9 @@ __device__ __forceinline__ void level_stream_rot(const PassArgs& A, float* S, fl
     const int xm = xc & mask;
     copy[unit * 64 + lane] = S[r1 * A.rs + xm + (xm >> 5)];
   }
-  __syncthreads();
+  // with one segment per row pair, a unit's copy is written and read by the same wave (LDS
+  // accesses of a wave complete in order): only split rows need the block to wait here
+  if (log2s > 0) __syncthreads();
   for (int u = 0; u < units; ++u) {
     const int unit = wave + u * waves;
     const int pair = unit >> log2s, seg = unit & ((1 << log2s) - 1);
@@ -1257,12 +1240,15 @@ __global__ void __launch_bounds__(512) fht_cols_kernel(PassArgs A) {
       __syncthreads();
     }
     float* dst = A.out + (size_t)bq * N * N;
-    for (int e = tid; e < R * W; e += T) {
-      const int rho = e >> A.log2w, u = e & (W - 1);
+    // a wave writes 64 consecutive columns of one row (W >= 64): row, output row and rotation
+    // are wave-uniform
+    const int lane = tid & 63;
+    for (int e0 = wave_id() << 6; e0 < R * W; e0 += T) {
+      const int rho = e0 >> A.log2w, u = (e0 & (W - 1)) + lane;
       const int i = brev_bits(rho, F);
       const int orow = (((j << F) + i) << k_lo) + v;
       const int o = (v * i) & mask;
-      dst[(size_t)orow * N + ((cx + u + o) & mask)] = S[cat(rho, H + u, rs)];
+      dst[orow * N + ((cx + u + o) & mask)] = S[cat(rho, H + u, rs)];
     }
   }
 }

@@ -591,7 +591,10 @@ int fbp_plan(const fbp_plan_desc* d, fbp_plan_t* out) {
   const int C = std::max(1, std::min(64, N / 32));
   p->log2c = ilog2(C);
   p->log2l = p->log2n - p->log2c;
-  p->rs = N + (N >> p->log2l) + 1;
+  // LDS row stride: N words plus one skew word per L.  It is 33 C words, = C (mod 64): with a
+  // wave holding 64 / C rows of C chunks, the filter's chunk-strided accesses (bank 33 c + C r
+  // mod 64) then hit 64 distinct banks
+  p->rs = N + (N >> p->log2l);
   // levels per pass: the tile of 2^F full rows must fit the LDS and 2^F * C <= 1024 threads
   int lds_max = 0;
   if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device) !=

@@ -9,6 +9,6 @@ from .api import (  # noqa: F401
     fbp_reconstruct, fbp_fit_ramp_iir, fbp_direct_parallel, fbp_direct_filter,
     fbp_direct_backproject, fbp_direct_linogram, fbp_filter_coef_grad, load_library, strerror,
     fbp_reconstruct_many, fbp_graph_create, Graph, fbp_resample_sinogram,
-    fbp_reconstruct_sinogram,
+    fbp_reconstruct_sinogram, fbp_reconstruct_sinogram_padded,
 )
 from .autograd import FBPReconstruct, fbp_reconstruct_autograd  # noqa: F401,E402

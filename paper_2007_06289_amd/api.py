@@ -542,3 +542,18 @@ def fbp_reconstruct_sinogram(plan: Plan, sino: torch.Tensor, img: torch.Tensor |
            "fbp_reconstruct_sinogram")
     return img
 
+
+
+def fbp_reconstruct_sinogram_padded(plan2: Plan, sino: torch.Tensor, n: int,
+                                    img2: torch.Tensor | None = None,
+                                    work: torch.Tensor | None = None) -> torch.Tensor:
+    """Objects that reach outside the disc of radius 0.34 n, where the cyclic shift axis of the
+    n-shift linogram would fold their projections onto themselves: resample and reconstruct
+    on the 2n grid (same pixel size and centre; its 0.34 * 2n disc holds the inscribed circle
+    of the n x n image) and return the central n x n part as a view of the 2n image.
+    ``plan2`` is a plan for 2n."""
+    if plan2.n != 2 * n:
+        raise ValueError(f"plan2 is for N={plan2.n}, need 2n = {2 * n}")
+    img2 = fbp_reconstruct_sinogram(plan2, sino, img2, work)
+    o = n // 2
+    return img2[:, o:o + n, o:o + n]

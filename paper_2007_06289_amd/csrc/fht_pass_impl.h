@@ -251,7 +251,7 @@ __device__ void filter_tile(const PassArgs& A, float* S, int q, int row0) {
 // group (first_pass_supported): the group's coefficients are then read with scalar loads,
 // which do not wait behind the vector loads of the next tile that are already in flight.
 template <int K>
-__device__ void filter_tile_aligned(const PassArgs& A, float* S, int q, int row0, float ct) {
+__device__ bool filter_tile_aligned(const PassArgs& A, float* S, int q, int row0, float ct) {
   constexpr int L = 32;
   int tid = threadIdx.x;
   asm volatile("" : "+v"(tid));
@@ -389,10 +389,32 @@ __device__ void filter_tile_aligned(const PassArgs& A, float* S, int q, int row0
       sta[0] = za;
     }
   }
-  __syncthreads();
+  __syncthreads();   // every chunk has read its samples and its neighbours' halo
+  // With C <= 32 the two rows that level 0 of the transposed transform pairs (tile rows 2k and
+  // 2k + 1) sit in lanes c and c + C of one wave.  Their window starts are equal (row0 is
+  // even), so in window coordinates the butterfly is lower[x] = r0[x] + r1[x] and upper[x] =
+  // r0[x] + r1[x - 1], cyclically: it is done here, on the scaled filter output in registers,
+  // and the rows are stored after level 0 (the same additions as the LDS level would do).
+  const bool level0 = A.log2c <= 5;
+  if (level0) {
+    const int lane = tid & 63;
+    const bool upper = (r & 1) != 0;
+    float v[L];
 #pragma unroll
-  for (int i = 0; i < L; ++i) rp[i] = ct * y[i];
+    for (int i = 0; i < L; ++i) v[i] = ct * y[i];
+    // r1[x - 1] at the start of the chunk: the last value of the previous chunk of this row
+    const float prev = __shfl(v[L - 1], (lane & ~(C - 1)) | ((c - 1) & (C - 1)));
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      const float p = __shfl_xor(v[i], C);
+      rp[i] = upper ? p + (i == 0 ? prev : v[i - 1]) : v[i] + p;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < L; ++i) rp[i] = ct * y[i];
+  }
   __syncthreads();
+  return level0;
 }
 
 // ---- F in-place transposed butterfly levels with lazy shifts ---------------------------------
@@ -913,10 +935,11 @@ __global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
       }
     }
     if (tl + (int)gridDim.x < A.total_tiles) issue(tl + gridDim.x);
-    if constexpr (K > 0) filter_tile_aligned<K>(A, S, q, row0, ct);
+    bool level0 = false;
+    if constexpr (K > 0) level0 = filter_tile_aligned<K>(A, S, q, row0, ct);
     {
       float* copy = S + (1 << A.log2r) * A.rs;
-      for (int l = 0; l < F; ++l) {
+      for (int l = level0 ? 1 : 0; l < F; ++l) {
         level_stream_rot<NBLK, (K > 0)>(A, S, copy, l, row0);
         __syncthreads();
       }

@@ -986,7 +986,7 @@ __device__ __forceinline__ int cat(int r, int c, int rs) { return r * rs + c + (
 // power-of-two shapes; each class is read through its own buffer resource, so a load needs
 // one 32-bit offset, and all of a thread's loads of a batch are in flight before it stores.
 // A float4 at a column that is a multiple of 4 never straddles a skew step, so its four LDS
-// words sit at one address plus 0..3.
+// words sit at one address plus 0..3.  The tile is stored after level 0 (below).
 template <int NCLS>
 __device__ void cols_load_tile(const PassArgs& A, float* S, int rs, const float* const* cls,
                                const int* col, int row0) {
@@ -1000,27 +1000,52 @@ __device__ void cols_load_tile(const PassArgs& A, float* S, int rs, const float*
 #pragma unroll
   for (int c = 0; c < NCLS; ++c)
     rsrc[c] = __builtin_amdgcn_make_buffer_rsrc((void*)cls[c], (short)0, N * N * 4, kBufferDword3);
-  auto put = [&](int c, int r, int lc, const u32x4& w) {
-    float* d = S + (c * R + r) * rs + lc + (lc >> 5);
-    d[0] = __uint_as_float(w.x);
-    d[1] = __uint_as_float(w.y);
-    d[2] = __uint_as_float(w.z);
-    d[3] = __uint_as_float(w.w);
+  // Level 0 of the transposed transform is done here, on the loaded values: it pairs tile rows
+  // 2m and 2m + 1 (relative shift 0), lower[x] = r0[x] + r1[x] and upper[x] = r0[x] +
+  // r1[x - 1], so each thread loads the same float4 column of both rows.  r1[x - 1] at the
+  // first column of a float4 is the previous float4's last value, held by the previous lane
+  // (the previous float4 of the row) except at the start of a wave's run, where it is read
+  // from memory; tile column 0 has no column below and stays as loaded (it only feeds
+  // outputs below the halo), as in the LDS levels.
+  auto butterfly = [&](int c, int m, int lc, const u32x4& a, const u32x4& b, float prev) {
+    const float a0 = __uint_as_float(a.x), a1 = __uint_as_float(a.y);
+    const float a2 = __uint_as_float(a.z), a3 = __uint_as_float(a.w);
+    const float b0 = __uint_as_float(b.x), b1 = __uint_as_float(b.y);
+    const float b2 = __uint_as_float(b.z), b3 = __uint_as_float(b.w);
+    float* lo = S + (c * R + 2 * m) * rs + lc + (lc >> 5);
+    float* up = lo + rs;
+    lo[0] = a0 + b0;
+    lo[1] = a1 + b1;
+    lo[2] = a2 + b2;
+    lo[3] = a3 + b3;
+    up[0] = lc == 0 ? b0 : a0 + prev;
+    up[1] = a1 + b0;
+    up[2] = a2 + b1;
+    up[3] = a3 + b2;
+    if (lc == 0) lo[0] = a0;
   };
+  const int lane = tid & 63;
   // main part: columns H .. H + W - 1 of the tile
-  constexpr int B = 4;
-  const int per = R << lw;
+  constexpr int B = 2;
+  const int per = (R >> 1) << lw;                 // float4 columns of the row pairs
   for (int base = tid; base < per; base += B * T) {
-    u32x4 v[NCLS][B];
+    u32x4 va[NCLS][B], vb[NCLS][B];
+    float pv[NCLS][B];
 #pragma unroll
     for (int c = 0; c < NCLS; ++c)
 #pragma unroll
       for (int k = 0; k < B; ++k) {
         const int e = base + k * T;
         if (e < per) {
-          const int r = e >> lw, j = e & ((1 << lw) - 1);
-          v[c][k] = __builtin_amdgcn_raw_buffer_load_b128(
-              rsrc[c], ((row0 + r) * N + col[c] + 4 * j) * 4, 0, 0);
+          const int m = e >> lw, j = e & ((1 << lw) - 1);
+          const int o0 = ((row0 + 2 * m) * N + col[c] + 4 * j) * 4;
+          va[c][k] = __builtin_amdgcn_raw_buffer_load_b128(rsrc[c], o0, 0, 0);
+          vb[c][k] = __builtin_amdgcn_raw_buffer_load_b128(rsrc[c], o0 + N * 4, 0, 0);
+          // the value below the float4 in row 2m + 1, from memory where no lane holds it
+          pv[c][k] = 0.f;
+          if ((j & 63) == 0 || lane == 0)
+            pv[c][k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+                rsrc[c], ((row0 + 2 * m + 1) * N + ((col[c] + 4 * j - 1) & mask)) * 4, 0, 0));
         }
       }
 #pragma unroll
@@ -1028,20 +1053,41 @@ __device__ void cols_load_tile(const PassArgs& A, float* S, int rs, const float*
 #pragma unroll
       for (int k = 0; k < B; ++k) {
         const int e = base + k * T;
-        if (e < per) put(c, e >> lw, H + 4 * (e & ((1 << lw) - 1)), v[c][k]);
+        // every lane takes part in the shuffle (the float4 of the previous lane)
+        const float w = __shfl_up(__uint_as_float(vb[c][k].w), 1);
+        if (e < per) {
+          const int j = e & ((1 << lw) - 1);
+          const float prev = ((j & 63) == 0 || lane == 0) ? pv[c][k] : w;
+          butterfly(c, e >> lw, H + 4 * j, va[c][k], vb[c][k], prev);
+        }
       }
   }
   // halo: columns 0 .. H - 1 of the tile, source columns col[c] - H .. col[c] - 1 cyclically
-  const int perh = R << lh;
-  for (int e = tid; e < perh; e += T) {
-    const int r = e >> lh, j = e & ((1 << lh) - 1);
-    u32x4 v[NCLS];
+  const int perh = (R >> 1) << lh;
+  for (int e0 = tid - lane; e0 < perh; e0 += T) {   // whole waves, for the shuffle
+    const int e = e0 + lane;
+    const int m = e >> lh, j = e & ((1 << lh) - 1);
+    u32x4 va[NCLS], vb[NCLS];
+    float pv[NCLS];
 #pragma unroll
-    for (int c = 0; c < NCLS; ++c)
-      v[c] = __builtin_amdgcn_raw_buffer_load_b128(
-          rsrc[c], ((row0 + r) * N + ((col[c] - H + 4 * j) & mask)) * 4, 0, 0);
+    for (int c = 0; c < NCLS; ++c) {
+      va[c] = u32x4{0, 0, 0, 0};
+      vb[c] = u32x4{0, 0, 0, 0};
+      pv[c] = 0.f;
+      if (e < perh) {
+        const int o0 = ((row0 + 2 * m) * N + ((col[c] - H + 4 * j) & mask)) * 4;
+        va[c] = __builtin_amdgcn_raw_buffer_load_b128(rsrc[c], o0, 0, 0);
+        vb[c] = __builtin_amdgcn_raw_buffer_load_b128(rsrc[c], o0 + N * 4, 0, 0);
+        if (j != 0 && lane == 0)
+          pv[c] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+              rsrc[c], ((row0 + 2 * m + 1) * N + ((col[c] - H + 4 * j - 1) & mask)) * 4, 0, 0));
+      }
+    }
 #pragma unroll
-    for (int c = 0; c < NCLS; ++c) put(c, r, 4 * j, v[c]);
+    for (int c = 0; c < NCLS; ++c) {
+      const float w = __shfl_up(__uint_as_float(vb[c].w), 1);
+      if (e < perh) butterfly(c, m, 4 * j, va[c], vb[c], lane == 0 ? pv[c] : w);
+    }
   }
 }
 
@@ -1184,7 +1230,7 @@ __global__ void __launch_bounds__(512) fht_cols_kernel(PassArgs A) {
     }
     __syncthreads();
     const int pad = 64 * ((wt + 63) >> 6) - wt;
-    for (int l = 0; l < F; ++l) {
+    for (int l = 1; l < F; ++l) {     // level 0 was done by the loader
       if (((wt + 63) >> 6) == 5) cols_level_fast<5>(S, rs, A.log2r, 2, pad, l);
       else cols_level(S, rs, A.log2r, 2, wt, l);
       __syncthreads();
@@ -1257,7 +1303,7 @@ __global__ void __launch_bounds__(512) fht_cols_kernel(PassArgs A) {
     }
     __syncthreads();
     const int pad = 64 * ((wt + 63) >> 6) - wt;
-    for (int l = 0; l < F; ++l) {
+    for (int l = 1; l < F; ++l) {     // level 0 was done by the loader
       if (((wt + 63) >> 6) == 5) cols_level_fast<5>(S, rs, A.log2r, 1, pad, l);
       else cols_level(S, rs, A.log2r, 1, wt, l);
       __syncthreads();

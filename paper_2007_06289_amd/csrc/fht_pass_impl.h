@@ -154,8 +154,9 @@ __device__ void filter_tile(const PassArgs& A, float* S, int q, int row0) {
       ac = fmaf(bk[k], xc[k], ac);
       aa = fmaf(bk[k], xa[k], aa);
     }
+    // oldest state first: the previous output enters last, one FMA per step on the chain
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
+    for (int k = K - 1; k >= 0; --k) {
       ac = fmaf(-ak[k], stc[k], ac);
       aa = fmaf(-ak[k], sta[k], aa);
     }
@@ -220,7 +221,7 @@ __device__ void filter_tile(const PassArgs& A, float* S, int q, int row0) {
       const int i = s, j = L - 1 - s;
       float zc = 0.f, za = 0.f;
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
+      for (int k = K - 1; k >= 0; --k) {
         zc = fmaf(-ak[k], stc[k], zc);
         za = fmaf(-ak[k], sta[k], za);
       }
@@ -306,8 +307,9 @@ __device__ bool filter_tile_aligned(const PassArgs& A, float* S, int q, int row0
       ac = fmaf(bk[k], xc[k], ac);
       aa = fmaf(bk[k], xa[k], aa);
     }
+    // oldest state first: the previous output enters last, one FMA per step on the chain
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
+    for (int k = K - 1; k >= 0; --k) {
       ac = fmaf(-ak[k], stc[k], ac);
       aa = fmaf(-ak[k], sta[k], aa);
     }
@@ -374,7 +376,7 @@ __device__ bool filter_tile_aligned(const PassArgs& A, float* S, int q, int row0
       const int i = s, j = L - 1 - s;
       float zc = 0.f, za = 0.f;
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
+      for (int k = K - 1; k >= 0; --k) {
         zc = fmaf(-ak[k], stc[k], zc);
         za = fmaf(-ak[k], sta[k], za);
       }

@@ -117,14 +117,19 @@ std::vector<int> split_levels(int n, int fmax) {
 
 // Default back-projection schedule.  Below 256 every pass holds full rows (split_levels).  From
 // 256 on the passes after the first are column-tiled, which lets them fuse kColsLevels levels
-// whatever the row length, so: as few passes as possible, kColsLevels levels in each later
-// pass, the rest (at least two levels) in the first.  Measured fastest on MI355X among all
+// whatever the row length, so: as few passes as possible; with two passes the levels split
+// evenly (the first pass takes the larger half); with more, kColsLevels levels in each later
+// pass and the rest (at least two levels) in the first.  Measured fastest on MI355X among all
 // groupings (N = 256 .. 4096).
 constexpr int kColsLevels = 5;
 std::vector<int> backprojection_levels(int n, int fmax) {
   if (n < 8 || n <= fmax) return split_levels(n, fmax);
   int P = 2;
   while (fmax + kColsLevels * (P - 1) < n) ++P;
+  if (P == 2) {
+    const int first = std::min(fmax, (n + 1) / 2);
+    return {first, n - first};
+  }
   std::vector<int> v(P, kColsLevels);
   v[0] = n - kColsLevels * (P - 1);
   for (int i = P - 1; v[0] < 2 && i >= 1; --i) {   // first pass: at least two levels

@@ -563,6 +563,18 @@ __device__ __forceinline__ void level_stream_fast(const PassArgs& A, float* S, f
   }
 }
 
+// Lane L receives v from lane L - 1 and lane 0 receives `first` (DPP wave shift right by one).
+__device__ __forceinline__ float lanes_shift_up(float v, float first) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(first), __float_as_int(v),
+                                                    0x138, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float lane63(float v) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+__device__ __forceinline__ float uniform_float(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
 // Streaming level for a tile whose rows start with the rotations sigma of their filtering
 // windows (ROT): the butterfly inputs then differ by d = (sigma_a - sigma_b) - J, which can be
 // positive.  Units with d <= 0 walk down from the top block with a copy of the 64 columns below
@@ -613,13 +625,23 @@ __device__ __forceinline__ void level_stream_rot(const PassArgs& A, float* S, fl
     float* row1p = S + r1 * A.rs;
     const int x0 = seg * W;
     const float* cp = copy + unit * 64;
+    // The second input of column x, row1[x + d - 1], is the first input of column x - 1: lane
+    // L takes it from lane L - 1 of the same block, lane 0 from lane 63 of the block below, so
+    // a column costs two LDS reads instead of three.
     if (d <= 0) {
       const int xb = x0 + 64 + lane;              // block 1
-      const int x1 = xb + d, x2 = xb + d - 1;     // >= x0 since -d + 1 <= 64
+      const int x1 = xb + d;                      // >= x0 since -d + 1 <= 64
       float* a0 = row0p + xb + (xb >> 5);
       float* w1 = row1p + xb + (xb >> 5);
       const float* a1 = row1p + x1 + (x1 >> 5);
-      const float* a2 = row1p + x2 + (x2 >> 5);
+      const int x = x0 + lane;                    // block 0
+      const int y1 = x + d, y2 = x + d - 1;
+      const int m1 = y1 & mask;
+      // walking down, the first input of the next block is read one block ahead (it lies below
+      // everything this walk has written); lane 63 of block 0's is inside the segment
+      float nxt;
+      if constexpr (NBLK >= 2) nxt = a1[66 * (NBLK - 2)];
+      else nxt = row1p[m1 + (m1 >> 5)];
 #pragma unroll
       for (int top = NBLK - 1; top >= 1; top -= 4) {
         float va[4], vb[4];
@@ -628,9 +650,11 @@ __device__ __forceinline__ void level_stream_rot(const PassArgs& A, float* S, fl
           const int k = top - u2;
           if (k >= 1) {
             const int off = 66 * (k - 1);
+            const float cur = nxt;
+            nxt = (k >= 2) ? a1[off - 66] : row1p[m1 + (m1 >> 5)];
             const float v0 = a0[off];
-            va[u2] = v0 + a1[off];
-            vb[u2] = v0 + a2[off];
+            va[u2] = v0 + cur;
+            vb[u2] = v0 + lanes_shift_up(cur, lane63(nxt));
           }
         }
 #pragma unroll
@@ -643,23 +667,22 @@ __device__ __forceinline__ void level_stream_rot(const PassArgs& A, float* S, fl
           }
         }
       }
-      const int x = x0 + lane;
-      const int y1 = x + d, y2 = x + d - 1;
-      const int m1 = y1 & mask, m2 = y2 & mask;
+      // block 0: nxt holds row1 at y1; inputs below x0 come from the copy (lane 0's always)
       const float v0 = row0p[x + (x >> 5)];
-      const float t1 = row1p[m1 + (m1 >> 5)];
-      const float t2 = row1p[m2 + (m2 >> 5)];
-      const float v1 = (y1 >= x0) ? t1 : cp[(y1 - x0 + 64) & 63];
+      const float t2 = lanes_shift_up(nxt, 0.f);
+      const float v1 = (y1 >= x0) ? nxt : cp[(y1 - x0 + 64) & 63];
       const float v2 = (y2 >= x0) ? t2 : cp[(y2 - x0 + 64) & 63];
       row0p[x + (x >> 5)] = v0 + v1;
       row1p[x + (x >> 5)] = v0 + v2;
     } else {
       const int xb = x0 + lane;                   // block 0
-      const int x1 = xb + d, x2 = xb + d - 1;
+      const int x1 = xb + d;
       float* a0 = row0p + xb + (xb >> 5);
       float* w1 = row1p + xb + (xb >> 5);
       const float* a1 = row1p + x1 + (x1 >> 5);
-      const float* a2 = row1p + x2 + (x2 >> 5);
+      // lane 0 of block 0 takes row1 at x0 + d - 1, inside the segment since 1 <= d <= 64
+      const int xs = x0 + d - 1;
+      float below63 = uniform_float(row1p[xs + (xs >> 5)]);
 #pragma unroll
       for (int bot = 0; bot <= NBLK - 2; bot += 4) {
         float va[4], vb[4];
@@ -668,9 +691,11 @@ __device__ __forceinline__ void level_stream_rot(const PassArgs& A, float* S, fl
           const int k = bot + u2;
           if (k <= NBLK - 2) {
             const int off = 66 * k;
+            const float cur = a1[off];
             const float v0 = a0[off];
-            va[u2] = v0 + a1[off];
-            vb[u2] = v0 + a2[off];
+            va[u2] = v0 + cur;
+            vb[u2] = v0 + lanes_shift_up(cur, below63);
+            below63 = lane63(cur);
           }
         }
 #pragma unroll
@@ -686,10 +711,10 @@ __device__ __forceinline__ void level_stream_rot(const PassArgs& A, float* S, fl
       // top block: reads above the segment come from the copy
       const int x = x0 + W - 64 + lane;
       const int y1 = x + d, y2 = x + d - 1;
-      const int m1 = y1 & mask, m2 = y2 & mask;
+      const int m1 = y1 & mask;
       const float v0 = row0p[x + (x >> 5)];
       const float t1 = row1p[m1 + (m1 >> 5)];
-      const float t2 = row1p[m2 + (m2 >> 5)];
+      const float t2 = lanes_shift_up(t1, below63);
       const int top_end = x0 + W;
       const float v1 = (y1 < top_end) ? t1 : cp[(y1 - top_end) & 63];
       const float v2 = (y2 < top_end) ? t2 : cp[(y2 - top_end) & 63];
@@ -862,6 +887,37 @@ __global__ void __launch_bounds__(1024) fht_combine_kernel(PassArgs A) {
   }
 }
 
+// Four consecutive columns x .. x + 3 (x a multiple of 4) of a skewed LDS row held with a
+// rotation o (column c at position (c - o) mod N), for a wave-uniform o.  The positions fall into
+// at most two 4-aligned groups, each inside one 32-column skew step and away from the wrap, so a
+// group is one address plus immediate offsets; which words go to which group depends only on
+// o mod 4, a wave-uniform branch.
+__device__ __forceinline__ void store4_rotated(float* row, int x, int o, int mask, float4 v) {
+  const int m = (-o) & 3;
+  const int g0 = (x - o - m) & mask, g1 = (g0 + 4) & mask;
+  float* a = row + g0 + (g0 >> 5);
+  float* b = row + g1 + (g1 >> 5);
+  switch (m) {
+    case 0: a[0] = v.x; a[1] = v.y; a[2] = v.z; a[3] = v.w; break;
+    case 1: a[1] = v.x; a[2] = v.y; a[3] = v.z; b[0] = v.w; break;
+    case 2: a[2] = v.x; a[3] = v.y; b[0] = v.z; b[1] = v.w; break;
+    default: a[3] = v.x; b[0] = v.y; b[1] = v.z; b[2] = v.w; break;
+  }
+}
+
+__device__ __forceinline__ float4 load4_rotated(const float* row, int x, int o, int mask) {
+  const int m = (-o) & 3;
+  const int g0 = (x - o - m) & mask, g1 = (g0 + 4) & mask;
+  const float* a = row + g0 + (g0 >> 5);
+  const float* b = row + g1 + (g1 >> 5);
+  switch (m) {
+    case 0: return make_float4(a[0], a[1], a[2], a[3]);
+    case 1: return make_float4(a[1], a[2], a[3], b[0]);
+    case 2: return make_float4(a[2], a[3], b[0], b[1]);
+    default: return make_float4(a[3], b[0], b[1], b[2]);
+  }
+}
+
 // ---- persistent first pass: filter + top levels, the next tile's rows prefetched ------------
 // Each block loops over tiles (b, q, v) with a stride of the grid; the global loads of the next
 // tile are issued into registers after the current tile is filtered, so they are in flight
@@ -880,19 +936,26 @@ __global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
   if (tl >= A.total_tiles) return;
   // Tile loads go through a buffer resource: the tile base and the per-load step stay in scalar
   // registers and every load shares one vector offset, so the prefetch holds only its data.
-  auto issue = [&](int t2) {
+  // The next tile's loads go out in two halves, one before this tile's filter and one before
+  // its levels, so that HBM stays busy through the filter, the levels and the write-out
+  // (this tile's stores drain meanwhile) instead of idling after one burst.
+  auto issue = [&](int t2, int half) {
     const int bq = t2 / tiles, v = t2 - bq * tiles;
     const float* base = A.in + ((size_t)bq * N + (v << F)) * N;
     const __amdgpu_buffer_rsrc_t rsrc =
         __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (N << F) * 4, kBufferDword3);
+    constexpr int H2 = (NV + 1) / 2;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
-      const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(rsrc, tid * 16, k * T * 16, 0);
-      pre[k] = make_float4(__uint_as_float(w.x), __uint_as_float(w.y), __uint_as_float(w.z),
-                           __uint_as_float(w.w));
+      if ((k < H2) == (half == 0)) {
+        const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(rsrc, tid * 16, k * T * 16, 0);
+        pre[k] = make_float4(__uint_as_float(w.x), __uint_as_float(w.y), __uint_as_float(w.z),
+                             __uint_as_float(w.w));
+      }
     }
   };
-  issue(tl);
+  issue(tl, 0);
+  issue(tl, 1);
   for (; tl < A.total_tiles; tl += gridDim.x) {
     // the thread index is passed through an empty asm once per tile, so per-thread addresses
     // are recomputed each iteration instead of being held in registers across the whole loop
@@ -909,13 +972,7 @@ __global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
       const int r = __builtin_amdgcn_readfirstlane(e4 >> A.log2n);
       // with the filter, row r is stored window-aligned: shift s at column s - sigma
       const int sg = K > 0 ? window_start_of(row0 + r, A.log2n, A.windowed) : 0;
-      const int x = (e4 - sg) & mask;
-      float* d = S + r * A.rs;
-      d[x + (x >> 5)] = pre[k].x;
-      const int x1 = (x + 1) & mask, x2 = (x + 2) & mask, x3 = (x + 3) & mask;
-      d[x1 + (x1 >> 5)] = pre[k].y;
-      d[x2 + (x2 >> 5)] = pre[k].z;
-      d[x3 + (x3 >> 5)] = pre[k].w;
+      store4_rotated(S + r * A.rs, e4, sg, mask, pre[k]);
     }
     __syncthreads();
     // the row factor is read before the next tile's loads go out (vector loads complete in
@@ -936,9 +993,11 @@ __global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
         }
       }
     }
-    if (tl + (int)gridDim.x < A.total_tiles) issue(tl + gridDim.x);
+    const bool more = tl + (int)gridDim.x < A.total_tiles;
+    if (more) issue(tl + gridDim.x, 0);
     bool level0 = false;
     if constexpr (K > 0) level0 = filter_tile_aligned<K>(A, S, q, row0, ct);
+    if (more) issue(tl + gridDim.x, 1);
     {
       float* copy = S + (1 << A.log2r) * A.rs;
       for (int l = level0 ? 1 : 0; l < F; ++l) {
@@ -960,14 +1019,7 @@ __global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
       const int i = brev_bits(rho, F);
       const int orow = (i << k_lo) + v;
       const int o = (sig0 + v * i) & mask;
-      const float* srow = S + rho * A.rs;
-      const int p0 = (x - o) & mask, p1 = (x + 1 - o) & mask;
-      const int p2 = (x + 2 - o) & mask, p3 = (x + 3 - o) & mask;
-      float4 w;
-      w.x = srow[p0 + (p0 >> 5)];
-      w.y = srow[p1 + (p1 >> 5)];
-      w.z = srow[p2 + (p2 >> 5)];
-      w.w = srow[p3 + (p3 >> 5)];
+      const float4 w = load4_rotated(S + rho * A.rs, x, o, mask);
       *reinterpret_cast<float4*>(dst + orow * N + x) = w;
     }
     __syncthreads();
@@ -1244,24 +1296,31 @@ __global__ void __launch_bounds__(512) fht_cols_kernel(PassArgs A) {
       for (int e4 = tid; e4 < n4; e4 += T) {
         const int i = e4 >> (A.log2w - 2), u = (e4 & ((W >> 2) - 1)) << 2;
         const int rho = brev_bits(i, F);
+        // H, W and u are multiples of 4, so each class's four columns are one aligned group
+        // inside a skew step: one address, immediate offsets (class 1 read backwards)
+        const float* p0 = s0 + cat(rho, H + u, rs);
+        const float* p1 = s1 + cat(rho, H + W - 4 - u, rs);
         float4 w;
-        w.x = s0[cat(rho, H + u, rs)] + s1[cat(rho, H + W - 1 - u, rs)];
-        w.y = s0[cat(rho, H + u + 1, rs)] + s1[cat(rho, H + W - 2 - u, rs)];
-        w.z = s0[cat(rho, H + u + 2, rs)] + s1[cat(rho, H + W - 3 - u, rs)];
-        w.w = s0[cat(rho, H + u + 3, rs)] + s1[cat(rho, H + W - 4 - u, rs)];
+        w.x = p0[0] + p1[3];
+        w.y = p0[1] + p1[2];
+        w.z = p0[2] + p1[1];
+        w.w = p0[3] + p1[0];
         *reinterpret_cast<float4*>(img + (size_t)(row0 + i) * N + cx + u) = w;
       }
     } else if (vec) {
       // image[cx + u][j R + i] += c2[i][cx + u] + c3[i][N - 1 - cx - u], four i per thread
       auto add4 = [&](int e4, float4 o) {
         const int i = (e4 & ((R >> 2) - 1)) << 2, u = e4 >> (A.log2r - 2);
-        const int r0 = brev_bits(i, F), r1 = brev_bits(i + 1, F);
-        const int r2 = brev_bits(i + 2, F), r3 = brev_bits(i + 3, F);
+        // i is a multiple of 4 and F >= 2: rows i + 1, i + 2, i + 3 sit 2^(F-1), 2^(F-2) and
+        // 3 2^(F-2) rows after row brev(i) in bit-reversed order
+        const int d1 = rs << (F - 1), d2 = rs << (F - 2);
+        const float* p0 = s0 + cat(brev_bits(i, F), H + u, rs);
+        const float* p1 = s1 + cat(brev_bits(i, F), H + W - 1 - u, rs);
         float4 w;
-        w.x = o.x + s0[cat(r0, H + u, rs)] + s1[cat(r0, H + W - 1 - u, rs)];
-        w.y = o.y + s0[cat(r1, H + u, rs)] + s1[cat(r1, H + W - 1 - u, rs)];
-        w.z = o.z + s0[cat(r2, H + u, rs)] + s1[cat(r2, H + W - 1 - u, rs)];
-        w.w = o.w + s0[cat(r3, H + u, rs)] + s1[cat(r3, H + W - 1 - u, rs)];
+        w.x = o.x + p0[0] + p1[0];
+        w.y = o.y + p0[d1] + p1[d1];
+        w.z = o.z + p0[d2] + p1[d2];
+        w.w = o.w + p0[d1 + d2] + p1[d1 + d2];
         *reinterpret_cast<float4*>(img + (size_t)(cx + u) * N + row0 + i) = w;
       };
 #pragma unroll

@@ -724,6 +724,126 @@ __device__ __forceinline__ void level_stream_rot(const PassArgs& A, float* S, fl
   }
 }
 
+// Two levels (l, l + 1) of the first pass in one LDS round trip (radix 4), for rows stored
+// with their window rotations.  A unit is four rows r0 = base + ib, r1 = r0 + 2^l,
+// r2 = r0 + 2^(l+1), r3 = r2 + 2^l (base a multiple of 2^(l+2), ib < 2^l).  With the shifts
+// d01, d23 of level l and e of level l + 1 (each relative to the frames the rows are held in),
+//   A0 = r0[x] + r1[x + d01]          A1 = r0[x] + r1[x + d01 - 1]
+//   A2(y) = r2[y] + r3[y + d23]       A3(y) = r2[y] + r3[y + d23 - 1]
+//   B0 = A0 + A2(x + e)   B2 = A0 + A2(x + e - 1)   B1 = A1 + A3(x + e - 1)   B3 = A1 + A3(x + e - 2)
+// which are the additions of the two levels done one after the other.  A lane holds column
+// x = 61 k - 3 + lane of block k and reads r0[x], r1[x + d01], r2[x + e], r3[x + e + d23]; every
+// "- 1" operand is the lane below's value, moved by a DPP lane shift.  B3 reaches three lanes
+// down (A3(x + e - 2) holds r3 at x + e + d23 - 3), so lanes 0..2 only feed their neighbours
+// and each block writes 61 columns.  Per column of a unit that is four reads and four writes
+// for two levels, against eight of each for two streaming levels.  All reads of the stage
+// finish (barrier) before any write, so the shifts may have any sign.
+// With OUT_FINAL the rows are written unskewed and already rotated for the write-out: tile row
+// rho's column x lands at word rho rs + ((x + sig0 + v brev(rho, F)) mod N).
+constexpr int kStageMaxBlocks = 9;    // blocks of 61 columns per wave and stage
+
+__device__ __forceinline__ int wrap_half(int d, int N) {
+  d &= N - 1;
+  return d > (N >> 1) ? d - N : d;
+}
+
+__device__ __forceinline__ float lanes_shift_up_any(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true));
+}
+
+// The stage gives every wave one unit and the blocks first, first + step, ... of it (so the
+// waves must outnumber the units), at most kStageMaxBlocks of them.
+__device__ __forceinline__ bool stage4_fits(const PassArgs& A) {
+  const int N = 1 << A.log2n;
+  const int waves = blockDim.x >> 6, units = (1 << A.log2r) >> 2;
+  if (waves < units) return false;
+  const int nb = (N + 60) / 61, step = waves / units;
+  return (nb + step - 1) / step <= kStageMaxBlocks;
+}
+
+template <bool ROT, bool OUT_FINAL>
+__device__ __forceinline__ void stage4(const PassArgs& A, float* S, int l, int row0, int sig0,
+                                       int v) {
+  const int N = 1 << A.log2n, mask = N - 1;
+  const int lane = threadIdx.x & 63, wave = wave_id();
+  const int log2u = A.log2r - 2;                 // units: R / 4
+  const int nb = (N + 60) / 61;
+  const int step = (blockDim.x >> 6) >> log2u;
+  const int first = wave >> log2u;
+  // the unit's rows, shifts and (for the final stage) output rotations, all wave-uniform
+  const int u = wave & ((1 << log2u) - 1);
+  const int pp = u >> l, ib = u & ((1 << l) - 1);
+  const int base = pp << (l + 2);
+  const int r0 = base + ib;
+  int s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  if constexpr (ROT) {
+    s0 = window_start_of(row0 + base, A.log2n, A.windowed);
+    s1 = window_start_of(row0 + base + (1 << l), A.log2n, A.windowed);
+    s2 = window_start_of(row0 + base + (2 << l), A.log2n, A.windowed);
+    s3 = window_start_of(row0 + base + (3 << l), A.log2n, A.windowed);
+  }
+  const int J = brev_bits(ib, l), J2 = brev_bits(ib, l + 1);
+  const int d01 = wrap_half(s0 - s1, N) - J;
+  const int d23 = wrap_half(s2 - s3, N) - J;
+  const int e = wrap_half(s0 - s2, N) - J2;
+  const int rs = A.rs;
+  float* p0 = S + r0 * rs;
+  float* p1 = p0 + (rs << l);
+  float* p2 = p0 + (rs << (l + 1));
+  float* p3 = p2 + (rs << l);
+  // blocks past the wave's last repeat it: the same values are computed and stored twice
+  float o0[kStageMaxBlocks], o1[kStageMaxBlocks], o2[kStageMaxBlocks], o3[kStageMaxBlocks];
+#pragma unroll
+  for (int j = 0; j < kStageMaxBlocks; ++j) {
+    const int blk = min(first + j * step, nb - 1);
+    const int c = blk * 61 - 3 + lane;
+    const int x0 = c & mask, x1 = (c + d01) & mask, x2 = (c + e) & mask;
+    const int x3 = (c + e + d23) & mask;
+    const float a = p0[x0 + (x0 >> 5)];
+    const float b = p1[x1 + (x1 >> 5)];
+    const float f = p2[x2 + (x2 >> 5)];
+    const float g = p3[x3 + (x3 >> 5)];
+    const float A0 = a + b;
+    const float A1 = a + lanes_shift_up_any(b);
+    const float A2e = f + g;
+    const float A3e = f + lanes_shift_up_any(g);
+    const float t = lanes_shift_up_any(A3e);
+    o0[j] = A0 + A2e;
+    o2[j] = A0 + lanes_shift_up_any(A2e);
+    o1[j] = A1 + t;
+    o3[j] = A1 + lanes_shift_up_any(t);
+  }
+  __syncthreads();
+  int y0 = 0, y1 = 0, y2 = 0, y3 = 0;
+  if constexpr (OUT_FINAL) {
+    const int F = A.levels;
+    y0 = sig0 + v * brev_bits(r0, F);
+    y1 = sig0 + v * brev_bits(r0 + (1 << l), F);
+    y2 = sig0 + v * brev_bits(r0 + (2 << l), F);
+    y3 = sig0 + v * brev_bits(r0 + (3 << l), F);
+  }
+#pragma unroll
+  for (int j = 0; j < kStageMaxBlocks; ++j) {
+    const int blk = min(first + j * step, nb - 1);
+    const int c = blk * 61 - 3 + lane;
+    if (lane >= 3 && c < N) {
+      if constexpr (OUT_FINAL) {
+        p0[(c + y0) & mask] = o0[j];
+        p1[(c + y1) & mask] = o1[j];
+        p2[(c + y2) & mask] = o2[j];
+        p3[(c + y3) & mask] = o3[j];
+      } else {
+        const int sk = c + (c >> 5);
+        p0[sk] = o0[j];
+        p1[sk] = o1[j];
+        p2[sk] = o2[j];
+        p3[sk] = o3[j];
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // Two-phase form for rows shorter than 64 columns: every thread reads all its butterfly inputs,
 // then writes.
 template <int L>
@@ -998,29 +1118,58 @@ __global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
     bool level0 = false;
     if constexpr (K > 0) level0 = filter_tile_aligned<K>(A, S, q, row0, ct);
     if (more) issue(tl + gridDim.x, 1);
+    const int sig0 = (K > 0) ? window_start_of(row0, A.log2n, A.windowed) : 0;
+    // levels: an odd one streams, the rest go two at a time; the last pair writes the rows
+    // unskewed and rotated for the write-out
+    bool unskewed = false;
     {
       float* copy = S + (1 << A.log2r) * A.rs;
-      for (int l = level0 ? 1 : 0; l < F; ++l) {
-        level_stream_rot<NBLK, (K > 0)>(A, S, copy, l, row0);
-        __syncthreads();
+      int l = level0 ? 1 : 0;
+      const bool radix4 = (F - l >= 2) && stage4_fits(A);
+      if (!radix4 || ((F - l) & 1)) {
+        const int stop = radix4 ? l + 1 : F;
+        for (; l < stop; ++l) {
+          level_stream_rot<NBLK, (K > 0)>(A, S, copy, l, row0);
+          __syncthreads();
+        }
+      }
+      for (; l < F; l += 2) {
+        if (l + 2 == F) {
+          stage4<(K > 0), true>(A, S, l, row0, sig0, v);
+          unskewed = true;
+        } else {
+          stage4<(K > 0), false>(A, S, l, row0, sig0, v);
+        }
       }
     }
-    const int sig0 = (K > 0) ? window_start_of(row0, A.log2n, A.windowed) : 0;
     float* dst = A.out + (size_t)bq * N * N;
     int stid = tid;
     asm volatile("" : "+v"(stid));
     // as in the deposit, a wave's 256 values lie in one row: row, output row and rotation are
     // wave-uniform, only the column is per lane
+    if (unskewed) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      const int e4 = (stid + k * T) << 2;
-      const int rho = __builtin_amdgcn_readfirstlane(e4 >> A.log2n);
-      const int x = e4 & mask;
-      const int i = brev_bits(rho, F);
-      const int orow = (i << k_lo) + v;
-      const int o = (sig0 + v * i) & mask;
-      const float4 w = load4_rotated(S + rho * A.rs, x, o, mask);
-      *reinterpret_cast<float4*>(dst + orow * N + x) = w;
+      for (int k = 0; k < NV; ++k) {
+        const int e4 = (stid + k * T) << 2;
+        const int rho = __builtin_amdgcn_readfirstlane(e4 >> A.log2n);
+        const int x = e4 & mask;
+        const int orow = (brev_bits(rho, F) << k_lo) + v;
+        // rs and x are multiples of 4: one 16-byte LDS read
+        const float4 w = *static_cast<const float4*>(__builtin_assume_aligned(S + rho * A.rs + x, 16));
+        *reinterpret_cast<float4*>(dst + orow * N + x) = w;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) {
+        const int e4 = (stid + k * T) << 2;
+        const int rho = __builtin_amdgcn_readfirstlane(e4 >> A.log2n);
+        const int x = e4 & mask;
+        const int i = brev_bits(rho, F);
+        const int orow = (i << k_lo) + v;
+        const int o = (sig0 + v * i) & mask;
+        const float4 w = load4_rotated(S + rho * A.rs, x, o, mask);
+        *reinterpret_cast<float4*>(dst + orow * N + x) = w;
+      }
     }
     __syncthreads();
   }

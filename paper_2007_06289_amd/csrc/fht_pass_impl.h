@@ -406,9 +406,23 @@ __device__ bool filter_tile_aligned(const PassArgs& A, float* S, int q, int row0
     for (int i = 0; i < L; ++i) v[i] = ct * y[i];
     // r1[x - 1] at the start of the chunk: the last value of the previous chunk of this row
     const float prev = __shfl(v[L - 1], (lane & ~(C - 1)) | ((c - 1) & (C - 1)));
+    // the partner lane is lane ^ C: for C = 32 and 16 one permlane swap per sample (no LDS
+    // traffic), else a shuffle
+    const int log2c = A.log2c;
 #pragma unroll
     for (int i = 0; i < L; ++i) {
-      const float p = __shfl_xor(v[i], C);
+      float p;
+      if (log2c == 5) {
+        const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]),
+                                                         __float_as_uint(v[i]), false, false);
+        p = __uint_as_float((lane & 32) ? sw[0] : sw[1]);
+      } else if (log2c == 4) {
+        const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[i]),
+                                                         __float_as_uint(v[i]), false, false);
+        p = __uint_as_float((lane & 16) ? sw[0] : sw[1]);
+      } else {
+        p = __shfl_xor(v[i], C);
+      }
       rp[i] = upper ? p + (i == 0 ? prev : v[i - 1]) : v[i] + p;
     }
   } else {

@@ -775,7 +775,10 @@ __device__ __forceinline__ bool stage4_fits(const PassArgs& A) {
   return (nb + step - 1) / step <= kStageMaxBlocks;
 }
 
-template <bool ROT, bool OUT_FINAL>
+// IN_SKEW: the stage reads skewed rows (from the filter or a streaming level); later stages
+// read the unskewed rows an earlier stage wrote.  Every stage writes unskewed rows: at their
+// frame positions, or (OUT_FINAL) rotated for the write-out.
+template <bool ROT, bool IN_SKEW, bool OUT_FINAL>
 __device__ __forceinline__ void stage4(const PassArgs& A, float* S, int l, int row0, int sig0,
                                        int v) {
   const int N = 1 << A.log2n, mask = N - 1;
@@ -813,10 +816,10 @@ __device__ __forceinline__ void stage4(const PassArgs& A, float* S, int l, int r
     const int c = blk * 61 - 3 + lane;
     const int x0 = c & mask, x1 = (c + d01) & mask, x2 = (c + e) & mask;
     const int x3 = (c + e + d23) & mask;
-    const float a = p0[x0 + (x0 >> 5)];
-    const float b = p1[x1 + (x1 >> 5)];
-    const float f = p2[x2 + (x2 >> 5)];
-    const float g = p3[x3 + (x3 >> 5)];
+    const float a = p0[IN_SKEW ? x0 + (x0 >> 5) : x0];
+    const float b = p1[IN_SKEW ? x1 + (x1 >> 5) : x1];
+    const float f = p2[IN_SKEW ? x2 + (x2 >> 5) : x2];
+    const float g = p3[IN_SKEW ? x3 + (x3 >> 5) : x3];
     const float A0 = a + b;
     const float A1 = a + lanes_shift_up_any(b);
     const float A2e = f + g;
@@ -847,11 +850,10 @@ __device__ __forceinline__ void stage4(const PassArgs& A, float* S, int l, int r
         p2[(c + y2) & mask] = o2[j];
         p3[(c + y3) & mask] = o3[j];
       } else {
-        const int sk = c + (c >> 5);
-        p0[sk] = o0[j];
-        p1[sk] = o1[j];
-        p2[sk] = o2[j];
-        p3[sk] = o3[j];
+        p0[c] = o0[j];
+        p1[c] = o1[j];
+        p2[c] = o2[j];
+        p3[c] = o3[j];
       }
     }
   }
@@ -1147,12 +1149,14 @@ __global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
           __syncthreads();
         }
       }
-      for (; l < F; l += 2) {
+      for (bool first_stage = true; l < F; l += 2, first_stage = false) {
         if (l + 2 == F) {
-          stage4<(K > 0), true>(A, S, l, row0, sig0, v);
+          if (first_stage) stage4<(K > 0), true, true>(A, S, l, row0, sig0, v);
+          else stage4<(K > 0), false, true>(A, S, l, row0, sig0, v);
           unskewed = true;
         } else {
-          stage4<(K > 0), false>(A, S, l, row0, sig0, v);
+          if (first_stage) stage4<(K > 0), true, false>(A, S, l, row0, sig0, v);
+          else stage4<(K > 0), false, false>(A, S, l, row0, sig0, v);
         }
       }
     }

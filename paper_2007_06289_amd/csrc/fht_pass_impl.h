@@ -102,15 +102,17 @@ __device__ void filter_tile(const PassArgs& A, float* S, int q, int row0) {
   const int t = row0 + r;
   const int g = ((q * N + t) * A.groups) / (4 * N);
   const float* cf = A.coef + (size_t)g * A.coef_stride;
+  int sig = A.sigma[t];
+  const float ct = A.scale[t];
+  // the row factor c_t scales the numerator: the recursion then yields c_t y directly
   float bk[K], ak[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    bk[k] = cf[k];
+    bk[k] = ct * cf[k];
     ak[k] = cf[K + k];
   }
   const float* phi = cf + 2 * K;
-  int sig = A.sigma[t];
-  const float ct = A.scale[t];
+  const float* hom = phi + kScanLevels * K * K;
   const int base = c * L;
   float* row = S + r * A.rs;
   const int log2l = A.log2l;
@@ -216,24 +218,18 @@ __device__ void filter_tile(const PassArgs& A, float* S, int q, int row0) {
       stc[k] = (c == 0) ? 0.f : pc;
       sta[k] = (c == C - 1) ? 0.f : pa;
     }
+    // carry correction: the carried-in state through the homogeneous response, oldest first
 #pragma unroll
     for (int s = 0; s < L; ++s) {
       const int i = s, j = L - 1 - s;
-      float zc = 0.f, za = 0.f;
+      float yc = y[i], ya = y[j];
 #pragma unroll
       for (int k = K - 1; k >= 0; --k) {
-        zc = fmaf(-ak[k], stc[k], zc);
-        za = fmaf(-ak[k], sta[k], za);
+        yc = fmaf(hom[k * L + s], stc[k], yc);
+        ya = fmaf(hom[k * L + s], sta[k], ya);
       }
-      y[i] += zc;
-      y[j] += za;
-#pragma unroll
-      for (int k = K - 1; k > 0; --k) {
-        stc[k] = stc[k - 1];
-        sta[k] = sta[k - 1];
-      }
-      stc[0] = zc;
-      sta[0] = za;
+      y[i] = yc;
+      y[j] = ya;
     }
   }
   __syncthreads();   // every chunk has read its samples and its neighbours' halo
@@ -241,7 +237,7 @@ __device__ void filter_tile(const PassArgs& A, float* S, int q, int row0) {
 #pragma unroll
   for (int i = 0; i < L; ++i) {
     const int s = (sig + base + i) & mask;
-    row[s + (s >> log2l)] = ct * y[i];
+    row[s + (s >> log2l)] = y[i];
   }
   __syncthreads();
 }
@@ -262,13 +258,15 @@ __device__ bool filter_tile_aligned(const PassArgs& A, float* S, int q, int row0
   const int t = row0 + r;
   const int g = __builtin_amdgcn_readfirstlane(((q * N + t) * A.groups) / (4 * N));
   cfloat* cf = as_constant(A.coef + (size_t)g * A.coef_stride);
+  // the row factor c_t scales the numerator (per lane: a wave holds 64 / C rows)
   float bk[K], ak[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    bk[k] = cf[k];
+    bk[k] = ct * cf[k];
     ak[k] = cf[K + k];
   }
   cfloat* phi = cf + 2 * K;
+  cfloat* hom = phi + kScanLevels * K * K;
   const int base = c * L;
   float* row = S + r * A.rs;
   float* rp = row + base + (base >> 5);       // window positions base .. base + 31
@@ -371,24 +369,18 @@ __device__ bool filter_tile_aligned(const PassArgs& A, float* S, int q, int row0
       stc[k] = (c == 0) ? 0.f : pc;
       sta[k] = (c == C - 1) ? 0.f : pa;
     }
+    // carry correction: the carried-in state through the homogeneous response, oldest first
 #pragma unroll
     for (int s = 0; s < L; ++s) {
       const int i = s, j = L - 1 - s;
-      float zc = 0.f, za = 0.f;
+      float yc = y[i], ya = y[j];
 #pragma unroll
       for (int k = K - 1; k >= 0; --k) {
-        zc = fmaf(-ak[k], stc[k], zc);
-        za = fmaf(-ak[k], sta[k], za);
+        yc = fmaf(hom[k * L + s], stc[k], yc);
+        ya = fmaf(hom[k * L + s], sta[k], ya);
       }
-      y[i] += zc;
-      y[j] += za;
-#pragma unroll
-      for (int k = K - 1; k > 0; --k) {
-        stc[k] = stc[k - 1];
-        sta[k] = sta[k - 1];
-      }
-      stc[0] = zc;
-      sta[0] = za;
+      y[i] = yc;
+      y[j] = ya;
     }
   }
   __syncthreads();   // every chunk has read its samples and its neighbours' halo
@@ -403,7 +395,7 @@ __device__ bool filter_tile_aligned(const PassArgs& A, float* S, int q, int row0
     const bool upper = (r & 1) != 0;
     float v[L];
 #pragma unroll
-    for (int i = 0; i < L; ++i) v[i] = ct * y[i];
+    for (int i = 0; i < L; ++i) v[i] = y[i];
     // r1[x - 1] at the start of the chunk: the last value of the previous chunk of this row
     const float prev = __shfl(v[L - 1], (lane & ~(C - 1)) | ((c - 1) & (C - 1)));
     // the partner lane is lane ^ C: for C = 32 and 16 one permlane swap per sample (no LDS
@@ -427,7 +419,7 @@ __device__ bool filter_tile_aligned(const PassArgs& A, float* S, int q, int row0
     }
   } else {
 #pragma unroll
-    for (int i = 0; i < L; ++i) rp[i] = ct * y[i];
+    for (int i = 0; i < L; ++i) rp[i] = y[i];
   }
   __syncthreads();
   return level0;

@@ -107,6 +107,22 @@ void transition_powers(const double* a, int K, int L, double* out /* [kScanLevel
   }
 }
 
+// Homogeneous response of the recursion over one chunk of L samples: h_k[s] is the output at
+// step s of y[s] = -sum_m a_m y[s-1-m] started from y[-1-k] = 1 (the other initial values 0).
+// A chunk's carry correction is then sum_k h_k[s] y_in[-1-k], K multiply-adds per sample.
+void homogeneous_table(const double* a, int K, int L, double* out /* [K][L] */) {
+  for (int k = 0; k < K; ++k) {
+    std::vector<double> z(L + K, 0.0);   // z[K + s] = y[s], z[K - 1 - m] = y[-1-m]
+    z[K - 1 - k] = 1.0;
+    for (int s = 0; s < L; ++s) {
+      double acc = 0.0;
+      for (int m = 0; m < K; ++m) acc -= a[m] * z[K + s - 1 - m];
+      z[K + s] = acc;
+    }
+    for (int s = 0; s < L; ++s) out[k * L + s] = z[K + s];
+  }
+}
+
 // Levels per pass: as few passes as LDS allows, balanced, extra levels to the later passes.
 std::vector<int> split_levels(int n, int fmax) {
   const int P = (n + fmax - 1) / fmax;
@@ -144,7 +160,7 @@ int upload_coefficients(fbp_plan_s* p) {
   const int K = kernel_order(K0);   // taps K0..K-1 are zero
   const int L = 1 << p->log2l;
   std::vector<float> host((size_t)G * p->coef_stride, 0.f);
-  std::vector<double> phi(kScanLevels * K * K);
+  std::vector<double> phi(kScanLevels * K * K), hom((size_t)K * L);
   for (int g = 0; g < G; ++g) {
     std::vector<double> bg(K, 0.0), ag(K, 0.0);
     for (int k = 0; k < K0; ++k) {
@@ -160,6 +176,9 @@ int upload_coefficients(fbp_plan_s* p) {
     transition_powers(ag.data(), K, L, phi.data());
     for (int i = 0; i < kScanLevels * K * K; ++i)
       host[(size_t)g * p->coef_stride + 2 * K + i] = (float)phi[i];
+    homogeneous_table(ag.data(), K, L, hom.data());
+    for (int i = 0; i < K * L; ++i)
+      host[(size_t)g * p->coef_stride + 2 * K + kScanLevels * K * K + i] = (float)hom[i];
   }
   if (hipStreamSynchronize(p->stream) != hipSuccess) return FBP_EDEVICE;
   if (hipMemcpy(p->d_coef, host.data(), host.size() * sizeof(float), hipMemcpyHostToDevice) !=
@@ -628,7 +647,7 @@ int fbp_plan(const fbp_plan_desc* d, fbp_plan_t* out) {
   p->levels = backprojection_levels(p->log2n, fmax);
   {
     const int KK = kernel_order(K);
-    p->coef_stride = 2 * KK + kScanLevels * KK * KK;
+    p->coef_stride = 2 * KK + kScanLevels * KK * KK + KK * (1 << p->log2l);
   }
 
   // per-row tables: c_t = k_t w_t (times k_t again for FHT-normalised input), window starts

@@ -39,7 +39,7 @@ struct PassArgs {
   int order;        // recursive filter order K, 0 = no filtering in this pass
   int groups;       // coefficient groups
   int coef_stride;  // floats per group in `coef`
-  const float* coef;   // per group: b[K], a[K], Phi_j[K][K] for j < kScanLevels
+  const float* coef;   // per group: b[K], a[K], Phi_j[K][K] for j < kScanLevels, h_k[L] for k < K
   const float* scale;  // [N] row factor c_t
   const int* sigma;    // [N] window start of row t
   int rs;              // LDS row stride in floats

@@ -1092,6 +1092,23 @@ __global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
     const int bq = tl / tiles, v = tl - bq * tiles;
     const int q = bq & 3;
     const int row0 = v << F;
+    // the row factors go out first (scalar loads): their latency hides behind the deposit
+    float ct = 0.f;
+    if constexpr (K > 0) {
+      // a wave holds 64 / C consecutive rows (at most 8 here): read their factors with scalar
+      // loads and let each lane pick its row's
+      const int rpw = 64 >> A.log2c;
+      const int wave = __builtin_amdgcn_readfirstlane(ltid >> 6);
+      // all eight factors in one go (the table has spare floats past row N - 1), no waits in
+      // between; lanes pick their row's
+      cfloat* sc = as_constant(A.scale + row0 + wave * rpw);
+      const int lr = (ltid & 63) >> A.log2c;
+      float f8[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) f8[k] = sc[k];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) ct = (lr == k) ? f8[k] : ct;
+    }
     // N >= 256 here (at least four 64-column blocks per unit), so the 256 consecutive values
     // of a wave's float4 lie in one row: the row and its window start are wave-uniform
 #pragma unroll
@@ -1103,24 +1120,6 @@ __global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
       store4_rotated(S + r * A.rs, e4, sg, mask, pre[k]);
     }
     __syncthreads();
-    // the row factor is read before the next tile's loads go out (vector loads complete in
-    // order); those loads then fly during the filter, the levels and the write-out
-    float ct = 0.f;
-    if constexpr (K > 0) {
-      // a wave holds 64 / C consecutive rows (at most 8 here): read their factors with scalar
-      // loads and let each lane pick its row's
-      const int rpw = 64 >> A.log2c;
-      const int wave = __builtin_amdgcn_readfirstlane(ltid >> 6);
-      cfloat* sc = as_constant(A.scale + row0 + wave * rpw);
-      const int lr = (ltid & 63) >> A.log2c;
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        if (k < rpw) {
-          const float v = sc[k];
-          ct = (lr == k) ? v : ct;
-        }
-      }
-    }
     const bool more = tl + (int)gridDim.x < A.total_tiles;
     if (more) issue(tl + gridDim.x, 0);
     bool level0 = false;

@@ -672,7 +672,7 @@ int fbp_plan(const fbp_plan_desc* d, fbp_plan_t* out) {
   p->scratch_floats = (size_t)p->max_batch * 4 * per_class;
   const int nscratch = scratch_needed(std::max(p->levels.size(), p->fwd_levels.size()));
   bool ok = hipMalloc(&p->d_coef, (size_t)G * p->coef_stride * sizeof(float)) == hipSuccess &&
-            hipMalloc(&p->d_scale, N * sizeof(float)) == hipSuccess &&
+            hipMalloc(&p->d_scale, (N + kScalePad) * sizeof(float)) == hipSuccess &&
             hipMalloc(&p->d_sigma, N * sizeof(int)) == hipSuccess;
   for (int i = 0; ok && i < nscratch; ++i)
     ok = hipMalloc(&p->d_scratch[i], p->scratch_floats * sizeof(float)) == hipSuccess;

@@ -7,6 +7,7 @@
 namespace fhtfbp {
 
 constexpr int kMaxOrder = 8;       // largest recursive-filter order supported
+constexpr int kScalePad = 8;       // the row-factor table has 8 spare floats (whole-block scalar loads)
 constexpr int kScanLevels = 6;     // chunk transition matrices Phi^(L 2^j), j < 6 (C <= 64)
 constexpr int kMaxPasses = 12;
 constexpr int kLdsBudget = 160 * 1024;

@@ -1398,6 +1398,95 @@ __device__ void cols_level_fast(float* S, int rs, int log2r, int ncls, int pad, 
   }
 }
 
+// Two levels (l, l + 1) of a column tile in one LDS round trip: the radix-4 form of the first
+// pass (see stage4) with the lazy shifts of a tile that carries no rotations (d01 = d23 = -J,
+// e = -J2, J = brev(ib, l), J2 = brev(ib, l + 1)).  Reads below column 0 are clamped: those
+// columns, like the ones the streaming form leaves untouched, only feed columns under the halo.
+// Tiles of 5 blocks of 61 columns (W + halo <= 305), UPW units (four rows of one class) per wave.
+template <int UPW>
+__device__ __forceinline__ void cols_stage4(float* S, int rs, int log2r, int l, int wt) {
+  constexpr int NB = 5;
+  const int lane = threadIdx.x & 63, wave = wave_id(), waves = blockDim.x >> 6;
+  const int R = 1 << log2r;
+  const int log2upc = log2r - 2;                   // units per class: R / 4
+  int rb[UPW], J[UPW], J2[UPW];
+#pragma unroll
+  for (int k = 0; k < UPW; ++k) {
+    const int unit = wave + k * waves;
+    const int cls = unit >> log2upc, u = unit & ((1 << log2upc) - 1);
+    const int pp = u >> l, ib = u & ((1 << l) - 1);
+    rb[k] = cls * R + (pp << (l + 2)) + ib;
+    J[k] = brev_bits(ib, l);
+    J2[k] = brev_bits(ib, l + 1);
+  }
+  float o0[UPW * NB], o1[UPW * NB], o2[UPW * NB], o3[UPW * NB];
+#pragma unroll
+  for (int k = 0; k < UPW; ++k) {
+    const float* p0 = S + rb[k] * rs;
+    const float* p1 = p0 + (rs << l);
+    const float* p2 = p0 + (rs << (l + 1));
+    const float* p3 = p2 + (rs << l);
+#pragma unroll
+    for (int blk = 0; blk < NB; ++blk) {
+      const int c = min(blk * 61 - 3 + lane, wt - 1);
+      const int x0 = max(c, 0), x1 = max(c - J[k], 0), x2 = max(c - J2[k], 0);
+      const int x3 = max(c - J2[k] - J[k], 0);
+      const float a = p0[x0 + (x0 >> 5)];
+      const float b = p1[x1 + (x1 >> 5)];
+      const float f = p2[x2 + (x2 >> 5)];
+      const float g = p3[x3 + (x3 >> 5)];
+      const float A0 = a + b;
+      const float A1 = a + lanes_shift_up_any(b);
+      const float A2e = f + g;
+      const float A3e = f + lanes_shift_up_any(g);
+      const float t = lanes_shift_up_any(A3e);
+      const int j = k * NB + blk;
+      o0[j] = A0 + A2e;
+      o2[j] = A0 + lanes_shift_up_any(A2e);
+      o1[j] = A1 + t;
+      o3[j] = A1 + lanes_shift_up_any(t);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < UPW; ++k) {
+    float* q = S + rb[k] * rs;
+#pragma unroll
+    for (int blk = 0; blk < NB; ++blk) {
+      const int c = blk * 61 - 3 + lane;
+      if (lane >= 3 && c < wt) {
+        const int j = k * NB + blk;
+        const int sk = c + (c >> 5);
+        q[sk] = o0[j];
+        q[(rs << l) + sk] = o1[j];
+        q[(rs << (l + 1)) + sk] = o2[j];
+        q[(rs << (l + 1)) + (rs << l) + sk] = o3[j];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Levels 1 .. F - 1 of a column tile (level 0 was done by the loader): radix-4 stages when the
+// tile has 5 blocks of 61 columns and one or two units per wave, else streaming levels; with an
+// odd count the first level streams.
+__device__ __forceinline__ void cols_levels(float* S, int rs, int log2r, int ncls, int wt, int F) {
+  const int waves = blockDim.x >> 6;
+  const int units = (ncls << log2r) >> 2;
+  const int pad = 64 * ((wt + 63) >> 6) - wt;
+  const bool r4 = F >= 3 && (wt + 60) / 61 == 5 && (units == waves || units == 2 * waves);
+  int l = 1;
+  for (; l < F && (!r4 || ((F - l) & 1)); ++l) {
+    if (((wt + 63) >> 6) == 5) cols_level_fast<5>(S, rs, log2r, ncls, pad, l);
+    else cols_level(S, rs, log2r, ncls, wt, l);
+    __syncthreads();
+  }
+  for (; l < F; l += 2) {
+    if (units == waves) cols_stage4<1>(S, rs, log2r, l, wt);
+    else cols_stage4<2>(S, rs, log2r, l, wt);
+  }
+}
+
 template <int NCLS>
 __global__ void __launch_bounds__(512) fht_cols_kernel(PassArgs A) {
   extern __shared__ float S[];
@@ -1441,12 +1530,7 @@ __global__ void __launch_bounds__(512) fht_cols_kernel(PassArgs A) {
       }
     }
     __syncthreads();
-    const int pad = 64 * ((wt + 63) >> 6) - wt;
-    for (int l = 1; l < F; ++l) {     // level 0 was done by the loader
-      if (((wt + 63) >> 6) == 5) cols_level_fast<5>(S, rs, A.log2r, 2, pad, l);
-      else cols_level(S, rs, A.log2r, 2, wt, l);
-      __syncthreads();
-    }
+    cols_levels(S, rs, A.log2r, 2, wt, F);
     const float* s0 = S;
     const float* s1 = S + R * rs;
     if (vec && !hpass) {
@@ -1521,12 +1605,7 @@ __global__ void __launch_bounds__(512) fht_cols_kernel(PassArgs A) {
       cols_load_tile<1>(A, S, rs, cl, cc, row0);
     }
     __syncthreads();
-    const int pad = 64 * ((wt + 63) >> 6) - wt;
-    for (int l = 1; l < F; ++l) {     // level 0 was done by the loader
-      if (((wt + 63) >> 6) == 5) cols_level_fast<5>(S, rs, A.log2r, 1, pad, l);
-      else cols_level(S, rs, A.log2r, 1, wt, l);
-      __syncthreads();
-    }
+    cols_levels(S, rs, A.log2r, 1, wt, F);
     float* dst = A.out + (size_t)bq * N * N;
     // a wave writes 64 consecutive columns of one row (W >= 64): row, output row and rotation
     // are wave-uniform

@@ -133,24 +133,22 @@ std::vector<int> split_levels(int n, int fmax) {
 
 // Default back-projection schedule.  Below 256 every pass holds full rows (split_levels).  From
 // 256 on the passes after the first are column-tiled, which lets them fuse kColsLevels levels
-// whatever the row length, so: as few passes as possible; with two passes the levels split
-// evenly (the first pass takes the larger half); with more, kColsLevels levels in each later
-// pass and the rest (at least two levels) in the first.  Measured fastest on MI355X among all
-// groupings (N = 256 .. 4096).
+// whatever the row length (two radix-4 stages after the loader's level 0), so: as few passes as
+// possible, kColsLevels levels in every column-tiled pass and the rest in the first; if that
+// leaves the first pass fewer than two levels, the middle passes give theirs up first.
+// Measured fastest on MI355X among all groupings (N = 256 .. 4096).
 constexpr int kColsLevels = 5;
 std::vector<int> backprojection_levels(int n, int fmax) {
   if (n < 8 || n <= fmax) return split_levels(n, fmax);
   int P = 2;
   while (fmax + kColsLevels * (P - 1) < n) ++P;
-  if (P == 2) {
-    const int first = std::min(fmax, (n + 1) / 2);
-    return {first, n - first};
-  }
   std::vector<int> v(P, kColsLevels);
   v[0] = n - kColsLevels * (P - 1);
-  for (int i = P - 1; v[0] < 2 && i >= 1; --i) {   // first pass: at least two levels
-    v[i] -= 1;
-    v[0] += 1;
+  for (int i = 1; v[0] < 2 && i < P; ++i) {   // first pass: at least two levels
+    while (v[0] < 2 && v[i] > 2) {
+      v[i] -= 1;
+      v[0] += 1;
+    }
   }
   return v;
 }

@@ -244,8 +244,8 @@ def test_empty_batch_and_errors(gpu_lib):
 
 def test_plan_pass_structure(gpu_lib):
     api = gpu_lib
-    expect = {4: [2], 64: [6], 128: [7], 256: [4, 4], 512: [5, 4], 1024: [5, 5],
-              2048: [2, 5, 4], 4096: [2, 5, 5]}
+    expect = {4: [2], 64: [6], 128: [7], 256: [3, 5], 512: [4, 5], 1024: [5, 5],
+              2048: [2, 4, 5], 4096: [2, 5, 5]}
     for N, lv in expect.items():
         with api.fbp_plan(N, 1, *_coef(2)) as plan:
             assert plan.passes() == lv

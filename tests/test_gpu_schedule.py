@@ -165,7 +165,7 @@ def test_graph_sees_new_coefficients_and_refuses_a_new_schedule(gpu_lib):
         want = api.fbp_reconstruct(plan, lino)
         torch.cuda.synchronize()
         assert torch.equal(img, want)
-        plan.set_schedule([3, 5], 8)
+        plan.set_schedule([4, 4], 8)                      # not the default ([3, 5])
         with pytest.raises(api.FbpError) as e:
             g.launch()
         assert e.value.code == api.FBP_EINVAL

@@ -247,8 +247,11 @@ __device__ void filter_tile(const PassArgs& A, float* S, int q, int row0) {
 // passes the row factor c_t, and guarantees that all rows of a wave lie in one coefficient
 // group (first_pass_supported): the group's coefficients are then read with scalar loads,
 // which do not wait behind the vector loads of the next tile that are already in flight.
-template <int K>
-__device__ bool filter_tile_aligned(const PassArgs& A, float* S, int q, int row0, float ct) {
+// `step_hook(s)` runs at the top of recursion step s (the caller uses it to issue the next
+// tile's loads a few at a time, so the texture unit takes them while the ALUs work).
+template <int K, typename Hook>
+__device__ bool filter_tile_aligned(const PassArgs& A, float* S, int q, int row0, float ct,
+                                    Hook&& step_hook) {
   constexpr int L = 32;
   int tid = threadIdx.x;
   asm volatile("" : "+v"(tid));
@@ -297,6 +300,8 @@ __device__ bool filter_tile_aligned(const PassArgs& A, float* S, int q, int row0
       xa[k] = xa[k - 1];
     }
     if ((s & 3) == 0) asm volatile("" ::: "memory");   // keeps at most 8 LDS reads in flight
+    step_hook(s);
+    if ((s & 7) == 0) __builtin_amdgcn_sched_barrier(0);   // the hook's work stays at step s
     xc[0] = rp[i];
     xa[0] = rp[j];
     float ac = 0.f, aa = 0.f;
@@ -1082,6 +1087,22 @@ __global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
       }
     }
   };
+  // one load of the first half (k < (NV + 1) / 2)
+  auto issue_one = [&](int t2, int k) {
+    const int bq = t2 / tiles, v = t2 - bq * tiles;
+    const float* base = A.in + ((size_t)bq * N + (v << F)) * N;
+    const __amdgpu_buffer_rsrc_t rsrc =
+        __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (N << F) * 4, kBufferDword3);
+    constexpr int H2 = (NV + 1) / 2;
+#pragma unroll
+    for (int kk = 0; kk < H2; ++kk) {
+      if (kk == k) {
+        const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(rsrc, tid * 16, kk * T * 16, 0);
+        pre[kk] = make_float4(__uint_as_float(w.x), __uint_as_float(w.y), __uint_as_float(w.z),
+                              __uint_as_float(w.w));
+      }
+    }
+  };
   issue(tl, 0);
   issue(tl, 1);
   for (; tl < A.total_tiles; tl += gridDim.x) {
@@ -1121,9 +1142,17 @@ __global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
     }
     __syncthreads();
     const bool more = tl + (int)gridDim.x < A.total_tiles;
-    if (more) issue(tl + gridDim.x, 0);
     bool level0 = false;
-    if constexpr (K > 0) level0 = filter_tile_aligned<K>(A, S, q, row0, ct);
+    if constexpr (K > 0) {
+      // the first half of the next tile's loads, one every 8 recursion steps (the last tile
+      // of a block reloads itself instead of branching: no branch splits the filter's code)
+      const int tn = more ? tl + (int)gridDim.x : tl;
+      level0 = filter_tile_aligned<K>(A, S, q, row0, ct, [&](int s) {
+        if ((s & 7) == 0) issue_one(tn, s >> 3);
+      });
+    } else {
+      if (more) issue(tl + gridDim.x, 0);
+    }
     if (more) issue(tl + gridDim.x, 1);
     const int sig0 = (K > 0) ? window_start_of(row0, A.log2n, A.windowed) : 0;
     // levels: an odd one streams, the rest go two at a time; the last pair writes the rows

@@ -749,8 +749,8 @@ __device__ __forceinline__ void level_stream_rot(const PassArgs& A, float* S, fl
 // and each block writes 61 columns.  Per column of a unit that is four reads and four writes
 // for two levels, against eight of each for two streaming levels.  All reads of the stage
 // finish (barrier) before any write, so the shifts may have any sign.
-// With OUT_FINAL the rows are written unskewed and already rotated for the write-out: tile row
-// rho's column x lands at word rho rs + ((x + sig0 + v brev(rho, F)) mod N).
+// The last stage of the pass (stage4_store) stores its outputs to HBM directly: tile row rho's
+// column x goes to column (x + sig0 + v brev(rho, F)) mod N of output row brev(rho, F) 2^k_lo + v.
 constexpr int kStageMaxBlocks = 9;    // blocks of 61 columns per wave and stage
 
 __device__ __forceinline__ int wrap_half(int d, int N) {
@@ -773,11 +773,10 @@ __device__ __forceinline__ bool stage4_fits(const PassArgs& A) {
 }
 
 // IN_SKEW: the stage reads skewed rows (from the filter or a streaming level); later stages
-// read the unskewed rows an earlier stage wrote.  Every stage writes unskewed rows: at their
-// frame positions, or (OUT_FINAL) rotated for the write-out.
-template <bool ROT, bool IN_SKEW, bool OUT_FINAL>
-__device__ __forceinline__ void stage4(const PassArgs& A, float* S, int l, int row0, int sig0,
-                                       int v) {
+// read the unskewed rows an earlier stage wrote.  The stage writes its rows unskewed, at their
+// frame positions (the last stage of a pass is stage4_store).
+template <bool ROT, bool IN_SKEW>
+__device__ __forceinline__ void stage4(const PassArgs& A, float* S, int l, int row0) {
   const int N = 1 << A.log2n, mask = N - 1;
   const int lane = threadIdx.x & 63, wave = wave_id();
   const int log2u = A.log2r - 2;                 // units: R / 4
@@ -828,33 +827,91 @@ __device__ __forceinline__ void stage4(const PassArgs& A, float* S, int l, int r
     o3[j] = A1 + lanes_shift_up_any(t);
   }
   __syncthreads();
-  int y0 = 0, y1 = 0, y2 = 0, y3 = 0;
-  if constexpr (OUT_FINAL) {
-    const int F = A.levels;
-    y0 = sig0 + v * brev_bits(r0, F);
-    y1 = sig0 + v * brev_bits(r0 + (1 << l), F);
-    y2 = sig0 + v * brev_bits(r0 + (2 << l), F);
-    y3 = sig0 + v * brev_bits(r0 + (3 << l), F);
-  }
 #pragma unroll
   for (int j = 0; j < kStageMaxBlocks; ++j) {
     const int blk = min(first + j * step, nb - 1);
     const int c = blk * 61 - 3 + lane;
     if (lane >= 3 && c < N) {
-      if constexpr (OUT_FINAL) {
-        p0[(c + y0) & mask] = o0[j];
-        p1[(c + y1) & mask] = o1[j];
-        p2[(c + y2) & mask] = o2[j];
-        p3[(c + y3) & mask] = o3[j];
-      } else {
-        p0[c] = o0[j];
-        p1[c] = o1[j];
-        p2[c] = o2[j];
-        p3[c] = o3[j];
-      }
+      p0[c] = o0[j];
+      p1[c] = o1[j];
+      p2[c] = o2[j];
+      p3[c] = o3[j];
     }
   }
   __syncthreads();
+}
+
+// The last stage of the first pass: as stage4, but each block's outputs go straight to HBM
+// (row brev(rho) 2^k_lo + v of the class, rotated by sig0 + v brev(rho)), one 4-byte store per
+// lane and row, as soon as they are computed.  Nothing is written back to LDS, so the stage
+// needs no barrier between its reads and its stores (the caller's end-of-tile barrier guards
+// the reuse of LDS), and there is no separate write-out.
+template <bool ROT, bool IN_SKEW>
+__device__ __forceinline__ void stage4_store(const PassArgs& A, const float* S, int l, int row0,
+                                             int sig0, int v, float* dst, int k_lo) {
+  const int N = 1 << A.log2n, mask = N - 1;
+  const int F = A.levels;
+  const int lane = threadIdx.x & 63, wave = wave_id();
+  const int log2u = A.log2r - 2;
+  const int nb = (N + 60) / 61;
+  const int step = (blockDim.x >> 6) >> log2u;
+  const int first = wave >> log2u;
+  const int u = wave & ((1 << log2u) - 1);
+  const int pp = u >> l, ib = u & ((1 << l) - 1);
+  const int base = pp << (l + 2);
+  const int r0 = base + ib;
+  int s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  if constexpr (ROT) {
+    s0 = window_start_of(row0 + base, A.log2n, A.windowed);
+    s1 = window_start_of(row0 + base + (1 << l), A.log2n, A.windowed);
+    s2 = window_start_of(row0 + base + (2 << l), A.log2n, A.windowed);
+    s3 = window_start_of(row0 + base + (3 << l), A.log2n, A.windowed);
+  }
+  const int J = brev_bits(ib, l), J2 = brev_bits(ib, l + 1);
+  const int d01 = wrap_half(s0 - s1, N) - J;
+  const int d23 = wrap_half(s2 - s3, N) - J;
+  const int e = wrap_half(s0 - s2, N) - J2;
+  const int rs = A.rs;
+  const float* p0 = S + r0 * rs;
+  const float* p1 = p0 + (rs << l);
+  const float* p2 = p0 + (rs << (l + 1));
+  const float* p3 = p2 + (rs << l);
+  const int i0 = brev_bits(r0, F), i1 = brev_bits(r0 + (1 << l), F);
+  const int i2 = brev_bits(r0 + (2 << l), F), i3 = brev_bits(r0 + (3 << l), F);
+  float* q0 = dst + (size_t)((i0 << k_lo) + v) * N;
+  float* q1 = dst + (size_t)((i1 << k_lo) + v) * N;
+  float* q2 = dst + (size_t)((i2 << k_lo) + v) * N;
+  float* q3 = dst + (size_t)((i3 << k_lo) + v) * N;
+  const int y0 = sig0 + v * i0, y1 = sig0 + v * i1, y2 = sig0 + v * i2, y3 = sig0 + v * i3;
+  const int nbw = (nb - first + step - 1) / step;   // this wave's blocks
+#pragma unroll
+  for (int j = 0; j < kStageMaxBlocks; ++j) {
+    if (j < nbw) {
+      const int blk = first + j * step;
+      const int c = blk * 61 - 3 + lane;
+      const int x0 = c & mask, x1 = (c + d01) & mask, x2 = (c + e) & mask;
+      const int x3 = (c + e + d23) & mask;
+      const float a = p0[IN_SKEW ? x0 + (x0 >> 5) : x0];
+      const float b = p1[IN_SKEW ? x1 + (x1 >> 5) : x1];
+      const float f = p2[IN_SKEW ? x2 + (x2 >> 5) : x2];
+      const float g = p3[IN_SKEW ? x3 + (x3 >> 5) : x3];
+      const float A0 = a + b;
+      const float A1 = a + lanes_shift_up_any(b);
+      const float A2e = f + g;
+      const float A3e = f + lanes_shift_up_any(g);
+      const float t = lanes_shift_up_any(A3e);
+      const float B0 = A0 + A2e;
+      const float B2 = A0 + lanes_shift_up_any(A2e);
+      const float B1 = A1 + t;
+      const float B3 = A1 + lanes_shift_up_any(t);
+      if (lane >= 3 && c < N) {
+        q0[(c + y0) & mask] = B0;
+        q1[(c + y1) & mask] = B1;
+        q2[(c + y2) & mask] = B2;
+        q3[(c + y3) & mask] = B3;
+      }
+    }
+  }
 }
 
 // Two-phase form for rows shorter than 64 columns: every thread reads all its butterfly inputs,
@@ -1155,9 +1212,8 @@ __global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
     }
     if (more) issue(tl + gridDim.x, 1);
     const int sig0 = (K > 0) ? window_start_of(row0, A.log2n, A.windowed) : 0;
-    // levels: an odd one streams, the rest go two at a time; the last pair writes the rows
-    // unskewed and rotated for the write-out
-    bool unskewed = false;
+    // levels: an odd one streams, the rest go two at a time; the last pair stores the tile
+    bool stored = false;     // the last stage stored the tile to HBM itself
     {
       float* copy = S + (1 << A.log2r) * A.rs;
       int l = level0 ? 1 : 0;
@@ -1171,12 +1227,13 @@ __global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
       }
       for (bool first_stage = true; l < F; l += 2, first_stage = false) {
         if (l + 2 == F) {
-          if (first_stage) stage4<(K > 0), true, true>(A, S, l, row0, sig0, v);
-          else stage4<(K > 0), false, true>(A, S, l, row0, sig0, v);
-          unskewed = true;
+          float* dst = A.out + (size_t)bq * N * N;
+          if (first_stage) stage4_store<(K > 0), true>(A, S, l, row0, sig0, v, dst, k_lo);
+          else stage4_store<(K > 0), false>(A, S, l, row0, sig0, v, dst, k_lo);
+          stored = true;
         } else {
-          if (first_stage) stage4<(K > 0), true, false>(A, S, l, row0, sig0, v);
-          else stage4<(K > 0), false, false>(A, S, l, row0, sig0, v);
+          if (first_stage) stage4<(K > 0), true>(A, S, l, row0);
+          else stage4<(K > 0), false>(A, S, l, row0);
         }
       }
     }
@@ -1185,18 +1242,7 @@ __global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
     asm volatile("" : "+v"(stid));
     // as in the deposit, a wave's 256 values lie in one row: row, output row and rotation are
     // wave-uniform, only the column is per lane
-    if (unskewed) {
-#pragma unroll
-      for (int k = 0; k < NV; ++k) {
-        const int e4 = (stid + k * T) << 2;
-        const int rho = __builtin_amdgcn_readfirstlane(e4 >> A.log2n);
-        const int x = e4 & mask;
-        const int orow = (brev_bits(rho, F) << k_lo) + v;
-        // rs and x are multiples of 4: one 16-byte LDS read
-        const float4 w = *static_cast<const float4*>(__builtin_assume_aligned(S + rho * A.rs + x, 16));
-        *reinterpret_cast<float4*>(dst + orow * N + x) = w;
-      }
-    } else {
+    if (!stored) {
 #pragma unroll
       for (int k = 0; k < NV; ++k) {
         const int e4 = (stid + k * T) << 2;

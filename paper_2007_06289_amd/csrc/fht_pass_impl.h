@@ -403,24 +403,34 @@ __device__ bool filter_tile_aligned(const PassArgs& A, float* S, int q, int row0
     for (int i = 0; i < L; ++i) v[i] = y[i];
     // r1[x - 1] at the start of the chunk: the last value of the previous chunk of this row
     const float prev = __shfl(v[L - 1], (lane & ~(C - 1)) | ((c - 1) & (C - 1)));
-    // the partner lane is lane ^ C: for C = 32 and 16 one permlane swap per sample (no LDS
-    // traffic), else a shuffle
-    const int log2c = A.log2c;
+    // the partner lane is lane ^ C.  For C = 32 and 16 one permlane swap per sample does it:
+    // swapping X = v[i] with Y = (upper ? r1[x - 1] : v[i]) leaves r0[x] in the first output of
+    // every lane and, in the second, r1[x] for the lower row and r1[x - 1] for the upper one,
+    // so each lane's level-0 value is the sum of the two (no LDS traffic, no select after the
+    // swap).  Other C use a shuffle.
+    // (one loop per exchange kind: the choice is made once, not per sample)
+    if (A.log2c == 5) {
 #pragma unroll
-    for (int i = 0; i < L; ++i) {
-      float p;
-      if (log2c == 5) {
+      for (int i = 0; i < L; ++i) {
+        const float yv = upper ? (i == 0 ? prev : v[i - 1]) : v[i];
         const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]),
-                                                         __float_as_uint(v[i]), false, false);
-        p = __uint_as_float((lane & 32) ? sw[0] : sw[1]);
-      } else if (log2c == 4) {
-        const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[i]),
-                                                         __float_as_uint(v[i]), false, false);
-        p = __uint_as_float((lane & 16) ? sw[0] : sw[1]);
-      } else {
-        p = __shfl_xor(v[i], C);
+                                                         __float_as_uint(yv), false, false);
+        rp[i] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
       }
-      rp[i] = upper ? p + (i == 0 ? prev : v[i - 1]) : v[i] + p;
+    } else if (A.log2c == 4) {
+#pragma unroll
+      for (int i = 0; i < L; ++i) {
+        const float yv = upper ? (i == 0 ? prev : v[i - 1]) : v[i];
+        const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[i]),
+                                                         __float_as_uint(yv), false, false);
+        rp[i] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < L; ++i) {
+        const float p = __shfl_xor(v[i], C);
+        rp[i] = upper ? p + (i == 0 ? prev : v[i - 1]) : v[i] + p;
+      }
     }
   } else {
 #pragma unroll

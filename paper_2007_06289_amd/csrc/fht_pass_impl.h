@@ -888,11 +888,15 @@ __device__ __forceinline__ void stage4_store(const PassArgs& A, const float* S, 
   const float* p3 = p2 + (rs << l);
   const int i0 = brev_bits(r0, F), i1 = brev_bits(r0 + (1 << l), F);
   const int i2 = brev_bits(r0 + (2 << l), F), i3 = brev_bits(r0 + (3 << l), F);
-  float* q0 = dst + (size_t)((i0 << k_lo) + v) * N;
-  float* q1 = dst + (size_t)((i1 << k_lo) + v) * N;
-  float* q2 = dst + (size_t)((i2 << k_lo) + v) * N;
-  float* q3 = dst + (size_t)((i3 << k_lo) + v) * N;
-  const int y0 = sig0 + v * i0, y1 = sig0 + v * i1, y2 = sig0 + v * i2, y3 = sig0 + v * i3;
+  // stores through a buffer resource over the slice: the output row is a scalar byte offset,
+  // the cyclic column a 32-bit vector offset (two vector instructions per store)
+  const __amdgpu_buffer_rsrc_t out = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)dst, (short)0, (N * N) * 4, kBufferDword3);
+  const int so0 = (((i0 << k_lo) + v) * N) * 4, so1 = (((i1 << k_lo) + v) * N) * 4;
+  const int so2 = (((i2 << k_lo) + v) * N) * 4, so3 = (((i3 << k_lo) + v) * N) * 4;
+  const int m4 = N * 4 - 1;
+  const int y0 = (sig0 + v * i0) * 4, y1 = (sig0 + v * i1) * 4;
+  const int y2 = (sig0 + v * i2) * 4, y3 = (sig0 + v * i3) * 4;
   const int nbw = (nb - first + step - 1) / step;   // this wave's blocks
 #pragma unroll
   for (int j = 0; j < kStageMaxBlocks; ++j) {
@@ -915,10 +919,11 @@ __device__ __forceinline__ void stage4_store(const PassArgs& A, const float* S, 
       const float B1 = A1 + t;
       const float B3 = A1 + lanes_shift_up_any(t);
       if (lane >= 3 && c < N) {
-        q0[(c + y0) & mask] = B0;
-        q1[(c + y1) & mask] = B1;
-        q2[(c + y2) & mask] = B2;
-        q3[(c + y3) & mask] = B3;
+        const int c4 = c * 4;
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(B0), out, (c4 + y0) & m4, so0, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(B1), out, (c4 + y1) & m4, so1, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(B2), out, (c4 + y2) & m4, so2, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(B3), out, (c4 + y3) & m4, so3, 0);
       }
     }
   }

@@ -375,8 +375,11 @@ __device__ bool filter_tile_aligned(const PassArgs& A, float* S, int q, int row0
       sta[k] = (c == C - 1) ? 0.f : pa;
     }
     // carry correction: the carried-in state through the homogeneous response, oldest first
+    // (the table goes through scalar registers 8 steps at a time: the barriers keep the
+    // compiler from loading all of it at once and spilling scalar registers elsewhere)
 #pragma unroll
     for (int s = 0; s < L; ++s) {
+      if ((s & 7) == 0) asm volatile("" ::: "memory");
       const int i = s, j = L - 1 - s;
       float yc = y[i], ya = y[j];
 #pragma unroll

@@ -131,7 +131,7 @@ int fbp_direct_parallel(const float* sino, float* work, float* img, int32_t batc
  * recursive pair, exact line positions in place of dyadic patterns): every row (q, t) is read
  * over the same window as fbp_filter, filtered by the full-length FIR, scaled by c_t into
  * `work` ([batch][4N][N] floats, window order), and back-projected with linear interpolation at
- * the exact intercept of each pixel's line; the four classes are summed.  The accuracy judge
+ * the exact intercept of each pixel's line; the four classes are summed.  The accuracy yardstick
  * of the method (and the training target of the learned filter).  Theta(N^3) per slice. */
 int fbp_direct_linogram(const float* lino, float* work, float* img, int32_t batch, int32_t n,
                         void* stream);

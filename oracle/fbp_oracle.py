@@ -344,7 +344,7 @@ def fbp_fht(P: torch.Tensor, b: torch.Tensor, a: torch.Tensor, *, scale: bool = 
 
 
 # ---------------------------------------------------------------------------------------------
-# Sec. 2-3: direct FBP with the exact (full-length) ramp filter, the method's accuracy judge
+# Sec. 2-3: direct FBP with the exact (full-length) ramp filter, the method's accuracy yardstick
 # ---------------------------------------------------------------------------------------------
 
 def fir_ramp_full(x: torch.Tensor) -> torch.Tensor:

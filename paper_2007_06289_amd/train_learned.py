@@ -47,7 +47,7 @@ def main(argv=None):
     ap.add_argument("--order", type=int, default=4)
     ap.add_argument("--groups", type=int, default=8)
     ap.add_argument("--seed", type=int, default=5)
-    ap.add_argument("--out", default="gpurun_out/learned_model.pt")
+    ap.add_argument("--out", default="learned_model.pt")
     args = ap.parse_args(argv)
     log = lambda s: print(f"[learned] {s}", file=sys.stderr, flush=True)  # noqa: E731
     N, S, H = args.n, args.slices, args.holdout

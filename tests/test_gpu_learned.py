@@ -99,7 +99,7 @@ def test_cnn_backward_matches_oracle(gpu_lib):
 
 def test_learned_filter_lowers_error_against_direct_fbp(gpu_lib):
     """Order-4 coefficients per 8 angle groups plus the residual network, trained on noisy
-    phantom linograms against the direct FBP of the same data; judged by the FP64 direct FBP
+    phantom linograms against the direct FBP of the same data; measured against the FP64 direct FBP
     on held-out slices."""
     import paper_2007_06289_amd.learned as L
     api = gpu_lib
@@ -116,7 +116,7 @@ def test_learned_filter_lowers_error_against_direct_fbp(gpu_lib):
     before = L.relative_rmse(plain, noisy[te], target[te], mask)
     L.train(model, noisy[tr], target[tr], mask, steps=150, batch=8)
     after = L.relative_rmse(model, noisy[te], target[te], mask)
-    # the judge: FP64 direct FBP (oracle) on the held-out slices
+    # the yardstick: FP64 direct FBP (oracle) on the held-out slices
     ref = O.fbp_direct_linogram(noisy[te].cpu().double())
     with torch.no_grad():
         out_l = model(noisy[te]).cpu().double()
@@ -125,7 +125,7 @@ def test_learned_filter_lowers_error_against_direct_fbp(gpu_lib):
     e_l = float(torch.linalg.vector_norm((out_l - ref)[:, m]) / torch.linalg.vector_norm(ref[:, m]))
     e_p = float(torch.linalg.vector_norm((out_p - ref)[:, m]) / torch.linalg.vector_norm(ref[:, m]))
     print(f"held-out relative RMSE vs direct FBP: plain {before:.4f} learned {after:.4f}; "
-          f"FP64 judge: plain {e_p:.4f} learned {e_l:.4f}")
+          f"FP64 direct FBP: plain {e_p:.4f} learned {e_l:.4f}")
     plain.close()
     model.close()
     assert e_l < 0.8 * e_p

@@ -103,13 +103,13 @@ def test_padded_grid_handles_objects_outside_the_disc(gpu_lib):
     ells = I.random_ellipses(N, 12, seed=31, disc=0.65, batch=B)
     sino = I.parallel_sinogram(ells, N, P, n_det=D, device="cuda", dtype=torch.float32)
     b4, a4, _ = api.fbp_fit_ramp_iir(4, 256, dc_zero=True)
-    judge = O.fbp_direct_parallel(sino.cpu().double(), N)
+    yard = O.fbp_direct_parallel(sino.cpu().double(), N)
     with api.fbp_plan(N, B, b4, a4) as plan, api.fbp_plan(2 * N, B, b4, a4) as plan2:
         plain = api.fbp_reconstruct_sinogram(plan, sino)
         padded = api.fbp_reconstruct_sinogram_padded(plan2, sino, N)
         torch.cuda.synchronize()
-        e_plain = _rel(plain, judge)
-        e_pad = _rel(padded, judge)
+        e_plain = _rel(plain, yard)
+        e_pad = _rel(padded, yard)
         assert e_pad < 0.6 * e_plain, (e_plain, e_pad)
         bc = np.array(plan2._b, np.float32).astype(np.float64)
         ac = np.array(plan2._a, np.float32).astype(np.float64)

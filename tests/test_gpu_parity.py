@@ -166,6 +166,23 @@ def test_reconstruct_matches_oracle(gpu_lib, N, B, order):
     assert _rel_rmse(got, ref) < RTOL_RMSE
 
 
+@pytest.mark.parametrize("N,flags", [(512, 4), (1024, 4), (1024, 1), (1024, 2)])
+def test_reconstruct_flags_on_the_fused_first_pass(gpu_lib, N, flags):
+    """The fused first pass (filter, level 0 in registers, radix-4 stages, direct stores) with
+    the plan flags: 4 keeps the rows at shift 0 (no window rotation), 1 skips c_t, 2 multiplies
+    in one more k_t."""
+    api = gpu_lib
+    P = _phantom_lino(N, 1, seed=N + flags)
+    b, a = _coef(2)
+    with api.fbp_plan(N, 1, b, a, flags=flags) as plan:
+        got = api.fbp_reconstruct(plan, P.cuda())
+        torch.cuda.synchronize()
+    ref = O.fbp_fht(P.to(torch.float64), torch.tensor(b), torch.tensor(a),
+                    scale=not (flags & 1), input_is_fht=bool(flags & 2),
+                    windowed=not (flags & 4))
+    assert _rel_rmse(got, ref) < RTOL_RMSE
+
+
 def test_coefficient_rounding_sensitivity(gpu_lib):
     """With exact (FP64) coefficients in the oracle, order 2 still meets the bar because its
     balanced pair b = (b0, -b0) is exact in float32; order 4 shows the DC sensitivity."""

@@ -37,7 +37,7 @@ def parse():
     ap.add_argument("--order", type=int, default=2)
     ap.add_argument("--no-direct", action="store_true", help="skip the direct-FBP comparator")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-slices", type=int, default=48)
+    ap.add_argument("--cpu-slices", type=int, default=96)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (for scaling the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")

@@ -55,7 +55,8 @@ def parse():
 
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
-KIND_OF_KERNEL = (("fht_first_kernel", "first"), ("fht_cols_kernel<2>", "last"),
+KIND_OF_KERNEL = (("fht_first_kernel", "first"), ("fht_cols_kernel<2>", "last_vh"),
+                  ("fht_image_tile_kernel", "last"),
                   ("fht_cols_kernel<1>", "middle"), ("fht_rows_kernel", "rows"),
                   ("fht_combine_kernel", "combine"))
 
@@ -86,8 +87,8 @@ def _kind(name: str):
 def rocprof_summary(d: str, n: int, batch: int, order: int) -> str:
     """Text summary of a rocprofv3 run set: per-kernel durations (kernel trace) and HBM bytes per
     dispatch (FETCH_SIZE / WRITE_SIZE, scaled by what the same counters read for a plain copy
-    of known size), plus SQ counters.  The last pass kernel runs twice per step (classes 0+1,
-    then 2+3): its dispatches alternate last_v, last_h."""
+    of known size), plus SQ counters.  A last pass split by class pair runs its kernel twice
+    per step (classes 0+1, then 2+3): those dispatches alternate last_v, last_h."""
     import csv
     import glob
     from collections import defaultdict
@@ -100,7 +101,7 @@ def rocprof_summary(d: str, n: int, batch: int, order: int) -> str:
         return out
 
     def split_last(kind, seq):
-        return [("last_v" if i % 2 == 0 else "last_h") if kind == "last" else kind
+        return [("last_v" if i % 2 == 0 else "last_h") if kind == "last_vh" else kind
                 for i, _ in enumerate(seq)]
 
     lines = []
@@ -157,7 +158,7 @@ def rocprof_summary(d: str, n: int, batch: int, order: int) -> str:
         res["copy_factor"] = {"fetch": round(ff, 4), "write": round(fw, 4)}
         lines.append(f"copy calibration (1 GiB device copy): FETCH_SIZE {cf:.0f} KiB, WRITE_SIZE "
                      f"{cw:.0f} KiB per dispatch -> scale factors fetch x{ff:.3f}, write x{fw:.3f}")
-        alg = {"first": 32, "middle": 32, "last_v": 12, "last_h": 16}
+        alg = {"first": 32, "middle": 32, "last_v": 12, "last_h": 16, "last": 20}
         lines.append("HBM bytes per dispatch (counters x factor) vs algorithmic bytes:")
         for cname, tag, fac in (("FETCH_SIZE", "fetch", ff), ("WRITE_SIZE", "write", fw)):
             by = defaultdict(list)
@@ -230,9 +231,11 @@ def algorithmic_bytes(kind: str, n: int, levels: list[int]) -> float:
     middle: reads and writes the 4 classes (32 N^2)
     last_v: reads classes 0, 1 (8 N^2), writes the image (4 N^2)
     last_h: reads classes 2, 3 (8 N^2), reads and writes the image (8 N^2)
+    last:   reads the 4 classes (16 N^2), writes the image (4 N^2)
     """
     n2 = float(n) * n
     return {"first": 32 * n2, "middle": 32 * n2, "last_v": 12 * n2, "last_h": 16 * n2,
+            "last": 20 * n2,
             "forward": 20 * n2, "filter": 32 * n2}[kind]
 
 

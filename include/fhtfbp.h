@@ -171,7 +171,9 @@ int fbp_reconstruct_sinogram(fbp_plan_t plan, const float* sino, float* work, fl
 #define FBP_KERNEL_LAST_H  3  /* last pass, classes 2 + 3 added into image columns          */
 #define FBP_KERNEL_FORWARD 4  /* forward-transform passes                                    */
 #define FBP_KERNEL_FILTER  5  /* filter alone                                                */
-#define FBP_KERNEL_KINDS   6
+#define FBP_KERNEL_LAST    6  /* last pass of 5 levels, N >= 256: all four classes at once,   */
+                              /* over 128 x 128 image tiles (takes the place of LAST_V + _H) */
+#define FBP_KERNEL_KINDS   7
 
 /* enable != 0: clear and start recording a HIP event pair around every kernel the plan launches
  * (on the plan's stream, so the events time exactly that launch); enable == 0: stop.  Costs

@@ -205,7 +205,7 @@ class Plan:
         _check(load_library().fbp_plan_set_schedule(self.handle, lv, len(levels), int(log2w)),
                "fbp_plan_set_schedule")
 
-    KERNEL_KINDS = ("first", "middle", "last_v", "last_h", "forward", "filter")
+    KERNEL_KINDS = ("first", "middle", "last_v", "last_h", "forward", "filter", "last")
 
     def profile(self, enable: bool = True):
         """Start (clearing) or stop recording HIP events around every launch of this plan."""
@@ -214,8 +214,8 @@ class Plan:
 
     def profile_read(self) -> dict:
         """{kind: (total_ms, launches)} for the recorded launches (synchronises them)."""
-        ms = (ctypes.c_double * 6)()
-        n = (ctypes.c_int32 * 6)()
+        ms = (ctypes.c_double * len(self.KERNEL_KINDS))()
+        n = (ctypes.c_int32 * len(self.KERNEL_KINDS))()
         _check(load_library().fbp_plan_profile_read(self.handle, ms, n), "fbp_plan_profile_read")
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(self.KERNEL_KINDS) if n[i]}
 

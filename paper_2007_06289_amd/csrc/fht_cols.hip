@@ -15,4 +15,16 @@ hipError_t launch_cols(const PassArgs& a, int batch, hipStream_t stream) {
                        stream);
 }
 
+// The last back-projection pass over 128 x 128 image tiles (5 levels, N >= 256).
+hipError_t launch_image_tiles(const PassArgs& a, int batch, hipStream_t stream) {
+  if (a.levels != 5 || a.log2n < 8) return hipErrorInvalidValue;
+  PassArgs t = a;
+  t.log2r = 5;
+  t.log2w = 7;
+  t.halo = 32;
+  t.out_mode = OUT_IMG_V;
+  const int tpr = (1 << a.log2n) >> 7;
+  return launch_kernel(fht_image_tile_kernel, t, batch * tpr * tpr, 512, cols_lds_bytes(t), stream);
+}
+
 }  // namespace fhtfbp

@@ -1127,9 +1127,12 @@ __device__ __forceinline__ float4 load4_rotated(const float* row, int x, int o, 
 }
 
 // ---- persistent first pass: filter + top levels, the next tile's rows prefetched ------------
-// Each block loops over tiles (b, q, v) with a stride of the grid; the global loads of the next
-// tile are issued into registers after the current tile is filtered, so they are in flight
-// while the current tile's levels run and it is written out.
+// Each block loops over tiles (b, q, v) with a stride of the grid.  Per tile: the rows are
+// deposited in LDS rotated by their window starts; the filter runs (level 0 in registers at its
+// end) while the first half of the next tile's loads goes out a load every 8 recursion steps;
+// the second half goes out before the levels; levels 1 .. F - 1 run as radix-4 stages (an odd
+// one streams first), the last of which stores the tile to HBM itself.  The loads of the next
+// tile are in flight through all of it.
 template <int L, int K, int NBLK>
 __global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
   extern __shared__ float S[];
@@ -1280,7 +1283,8 @@ __global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
 // ---- column-tiled passes (no filter) ---------------------------------------------------------
 // With lazy shifts, an output column of a pass depends only on the 2^F - 1 columns below it, so a
 // tile can be a column block of W = 2^log2w columns plus a halo of `halo` columns below it, with
-// no wrap-around inside the tile.  NCLS = 2 (last back-projection pass): the block holds the
+// no wrap-around inside the tile.  NCLS = 2 (a last back-projection pass of other than 5
+// levels; one of 5 levels runs over square image tiles, further below): the block holds the
 // matching column blocks of a class pair and sums them into the image.  NCLS = 1 (middle pass):
 // one class, rows written with their pending rotation.
 __device__ __forceinline__ int cat(int r, int c, int rs) { return r * rs + c + (c >> 5); }
@@ -1291,8 +1295,9 @@ __device__ __forceinline__ int cat(int r, int c, int rs) { return r * rs + c + (
 // power-of-two shapes; each class is read through its own buffer resource, so a load needs
 // one 32-bit offset, and all of a thread's loads of a batch are in flight before it stores.
 // A float4 at a column that is a multiple of 4 never straddles a skew step, so its four LDS
-// words sit at one address plus 0..3.  The tile is stored after level 0 (below).
-template <int NCLS>
+// words sit at one address plus 0..3.  The tile is stored after level 0 (below).  B: float4
+// columns per class and thread whose loads are in flight together.
+template <int NCLS, int B = 2>
 __device__ void cols_load_tile(const PassArgs& A, float* S, int rs, const float* const* cls,
                                const int* col, int row0) {
   const int N = 1 << A.log2n, mask = N - 1;
@@ -1331,7 +1336,6 @@ __device__ void cols_load_tile(const PassArgs& A, float* S, int rs, const float*
   };
   const int lane = tid & 63;
   // main part: columns H .. H + W - 1 of the tile
-  constexpr int B = 2;
   const int per = (R >> 1) << lw;                 // float4 columns of the row pairs
   for (int base = tid; base < per; base += B * T) {
     u32x4 va[NCLS][B], vb[NCLS][B];
@@ -1495,10 +1499,10 @@ __device__ void cols_level_fast(float* S, int rs, int log2r, int ncls, int pad, 
 // pass (see stage4) with the lazy shifts of a tile that carries no rotations (d01 = d23 = -J,
 // e = -J2, J = brev(ib, l), J2 = brev(ib, l + 1)).  Reads below column 0 are clamped: those
 // columns, like the ones the streaming form leaves untouched, only feed columns under the halo.
-// Tiles of 5 blocks of 61 columns (W + halo <= 305), UPW units (four rows of one class) per wave.
-template <int UPW>
+// Tiles of NB blocks of 61 columns (W + halo <= 61 NB), UPW units (four rows of one class) per
+// wave.
+template <int UPW, int NB>
 __device__ __forceinline__ void cols_stage4(float* S, int rs, int log2r, int l, int wt) {
-  constexpr int NB = 5;
   const int lane = threadIdx.x & 63, wave = wave_id(), waves = blockDim.x >> 6;
   const int R = 1 << log2r;
   const int log2upc = log2r - 2;                   // units per class: R / 4
@@ -1575,8 +1579,8 @@ __device__ __forceinline__ void cols_levels(float* S, int rs, int log2r, int ncl
     __syncthreads();
   }
   for (; l < F; l += 2) {
-    if (units == waves) cols_stage4<1>(S, rs, log2r, l, wt);
-    else cols_stage4<2>(S, rs, log2r, l, wt);
+    if (units == waves) cols_stage4<1, 5>(S, rs, log2r, l, wt);
+    else cols_stage4<2, 5>(S, rs, log2r, l, wt);
   }
 }
 
@@ -1711,6 +1715,169 @@ __global__ void __launch_bounds__(512) fht_cols_kernel(PassArgs A) {
       dst[orow * N + ((cx + u + o) & mask)] = S[cat(rho, H + u, rs)];
     }
   }
+}
+
+// ---- last pass over square image tiles -------------------------------------------------------
+// All four classes of the last back-projection pass (2^5 levels to go) in one block, which owns
+// a 128 x 128 image tile: rows y0 .. y0 + 127, columns x0 .. x0 + 127 (eq 20-22).  Classes 0 and
+// 1 reach it through the 4 strips of rows y0 .. y0 + 127, column block x0:
+//     image[y][x] = c0[y][x] + c1[y][N-1-x];
+// classes 2 and 3 through the 4 strips of rows x0 .. x0 + 127, column block y0, transposed:
+//     image[y][x] += c2[x][y] + c3[x][N-1-y].
+// Each strip is a column tile of 32 rows by 128 + 32 columns (the halo below), run through the
+// loader's level 0 and levels 1 .. 4 in LDS, and added into accumulators held in registers; the
+// additions are those of the separate V and H launches in the same order, so the results are
+// bit-identical to them.  The image is written once and never read: 16 N^2 bytes in (plus a
+// quarter for the halo) and 4 N^2 out, against 28 N^2 (plus an eighth) for the two launches.
+// Thread t owns rows (t >> 5) + 16 m (m < 8) and columns (t & 31) + 32 b (b < 4) of the tile.
+// One strip of the square-tile pass in registers between its loads and its LDS deposit, so that
+// the next strip's loads are in flight while the current one runs its levels.  Thread t takes
+// row pair m = t >> 5: the float4 at tile column 32 + 4 j (j = t & 31) of both rows, and the
+// halo column j of both rows, for each class of the pair.
+struct StripRegs {
+  u32x4 a[2], b[2];   // main float4 of rows 2m, 2m + 1
+  float pv[2];        // row 2m + 1 one column below the float4 (j = 0 only)
+  float ha[2], hb[2]; // halo column j of rows 2m, 2m + 1
+};
+
+__device__ __forceinline__ void strip_issue(StripRegs& P, const float* c0, size_t nn, int col0,
+                                            int row0, int log2n) {
+  const int N = 1 << log2n, mask = N - 1;
+  const int tid = threadIdx.x, m = tid >> 5, j = tid & 31;
+#pragma unroll
+  for (int cl = 0; cl < 2; ++cl) {
+    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(c0 + cl * nn), (short)0, N * N * 4, kBufferDword3);
+    const int col = cl == 0 ? col0 : N - col0 - 128;
+    const int rowb = (row0 + 2 * m) * N;
+    const int o0 = (rowb + col + 4 * j) * 4;
+    P.a[cl] = __builtin_amdgcn_raw_buffer_load_b128(rsrc, o0, 0, 0);
+    P.b[cl] = __builtin_amdgcn_raw_buffer_load_b128(rsrc, o0 + N * 4, 0, 0);
+    P.pv[cl] = 0.f;
+    if (j == 0)
+      P.pv[cl] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+          rsrc, (rowb + N + ((col - 1) & mask)) * 4, 0, 0));
+    const int oh = (rowb + ((col - 32 + j) & mask)) * 4;
+    P.ha[cl] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsrc, oh, 0, 0));
+    P.hb[cl] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsrc, oh + N * 4, 0, 0));
+  }
+}
+
+// Level 0 on a strip's registers (lower = r0[x] + r1[x], upper = r0[x] + r1[x - 1]; tile column
+// 0 stays as loaded, as in the column loader) and the deposit into skewed LDS rows of stride rs.
+__device__ __forceinline__ void strip_deposit(const StripRegs& P, float* S, int rs) {
+  const int tid = threadIdx.x, m = tid >> 5, j = tid & 31;
+#pragma unroll
+  for (int cl = 0; cl < 2; ++cl) {
+    const float a0 = __uint_as_float(P.a[cl].x), a1 = __uint_as_float(P.a[cl].y);
+    const float a2 = __uint_as_float(P.a[cl].z), a3 = __uint_as_float(P.a[cl].w);
+    const float b0 = __uint_as_float(P.b[cl].x), b1 = __uint_as_float(P.b[cl].y);
+    const float b2 = __uint_as_float(P.b[cl].z), b3 = __uint_as_float(P.b[cl].w);
+    const float w = __shfl_up(b3, 1);                 // the previous float4 of row 2m + 1
+    const float prev = j == 0 ? P.pv[cl] : w;
+    float* lo = S + (cl * 32 + 2 * m) * rs;
+    float* up = lo + rs;
+    // main: tile columns 32 + 4 j .. 32 + 4 j + 3, skew 1 + j / 8
+    const int lc = 32 + 4 * j + 1 + (j >> 3);
+    lo[lc] = a0 + b0;
+    lo[lc + 1] = a1 + b1;
+    lo[lc + 2] = a2 + b2;
+    lo[lc + 3] = a3 + b3;
+    up[lc] = a0 + prev;
+    up[lc + 1] = a1 + b0;
+    up[lc + 2] = a2 + b1;
+    up[lc + 3] = a3 + b2;
+    // halo: tile column j (skew 0)
+    const float hbm = __shfl_up(P.hb[cl], 1);
+    lo[j] = j == 0 ? P.ha[cl] : P.ha[cl] + P.hb[cl];
+    up[j] = j == 0 ? P.hb[cl] : P.ha[cl] + hbm;
+  }
+}
+
+// At most 128 VGPRs, so that two blocks (16 waves) share a compute unit.
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+fht_image_tile_kernel(PassArgs A) {
+  extern __shared__ float S[];
+  constexpr int F = 5, R = 32, TT = 128, W = 128, H = 32, NS = TT / R;
+  constexpr int wt = W + H, rs = (wt + (wt >> 5) + 1) | 1;
+  const int tid = threadIdx.x;
+  const int N = 1 << A.log2n;
+  const int tpr = N / TT;                            // tiles per image row
+  const int per_slice = tpr * tpr;
+  // consecutive tiles of a row go to one XCD (blocks are dealt to the 8 XCDs in turn), so the
+  // halo columns that neighbouring tiles share are read through that XCD's L2
+  int id = blockIdx.x;
+  if ((gridDim.x & 7) == 0) id = (id & 7) * (gridDim.x >> 3) + (id >> 3);
+  const int b = id / per_slice, rest = id - b * per_slice;
+  const int ty = rest / tpr, tx = rest - ty * tpr;
+  const int y0 = ty * TT, x0 = tx * TT;
+  const size_t nn = (size_t)N * N;
+  const float* lino = A.in + (size_t)b * 4 * nn;
+  const int c = tid & 31, r = tid >> 5;
+  float acc[8][4];
+#pragma unroll
+  for (int m = 0; m < 8; ++m)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[m][k] = 0.f;
+  const float* s0 = S;
+  const float* s1 = S + R * rs;
+  StripRegs P;
+  strip_issue(P, lino, nn, x0, y0, A.log2n);
+  for (int ph = 0; ph < 2 * NS; ++ph) {
+    const bool hpart = ph >= NS;
+    const int s = hpart ? ph - NS : ph;
+    strip_deposit(P, S, rs);
+    __syncthreads();
+    if (ph + 1 < 2 * NS) {
+      // the next strip's loads go out now and land during this strip's levels
+      const int pn = ph + 1;
+      const bool hn = pn >= NS;
+      const int sn = hn ? pn - NS : pn;
+      strip_issue(P, lino + (hn ? 2 : 0) * nn, nn, hn ? y0 : x0, (hn ? x0 : y0) + sn * R, A.log2n);
+    }
+    // levels 1 .. 4: two radix-4 stages over 3 blocks of 61 columns, two units per wave
+    cols_stage4<2, 3>(S, rs, F, 1, wt);
+    cols_stage4<2, 3>(S, rs, F, 3, wt);
+    // LDS addresses with the skew written out (c, r < 32 and 16): one base per row and class,
+    // immediate offsets per column
+    if (!hpart) {
+      // tile rows 32 s .. 32 s + 31: this thread's rows r and r + 16 of the strip, columns
+      // x = c + 32 k: class 0 at H + x, class 1 at H + W - 1 - x
+#pragma unroll
+      for (int s2 = 0; s2 < NS; ++s2) {
+        if (s2 != s) continue;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int rho = brev_bits(r + 16 * h, F);
+          const float* p0 = s0 + rho * rs + (H + 1) + c;            // cat(rho, H + c)
+          const float* p1 = s1 + rho * rs + (H + W + 3) - c;        // cat(rho, H + W - 1 - c)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) acc[2 * s2 + h][k] += p0[33 * k] + p1[-33 * k];
+        }
+      }
+    } else {
+      // tile columns 32 s .. 32 s + 31 are strip rows: this thread's column c (strip row c),
+      // its rows u = r + 16 m: class 2 at column H + u, class 3 at H + W - 1 - u
+      const int rho = brev_bits(c, F);
+      const float* p0 = s0 + rho * rs + (H + 1) + r;                // cat(rho, H + r)
+      const float* p1 = s1 + rho * rs + (H + W + 3) - r;            // cat(rho, H + W - 1 - r)
+#pragma unroll
+      for (int s2 = 0; s2 < NS; ++s2) {
+        if (s2 != s) continue;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          const int o = 16 * m + (m >> 1);
+          acc[m][s2] = acc[m][s2] + p0[o] + p1[-o];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  float* img = A.out + (size_t)b * nn + (size_t)y0 * N + x0;
+#pragma unroll
+  for (int m = 0; m < 8; ++m)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) img[(size_t)(r + 16 * m) * N + c + 32 * k] = acc[m][k];
 }
 
 template <typename Kern>

@@ -203,6 +203,7 @@ Issue plan_issue(const fbp_plan_s* p) { return Issue{p->stream, p->profiling}; }
 
 hipError_t dispatch(fbp_plan_s* p, const PassArgs& A, int batch, int family, hipStream_t s) {
   if (family == PASS_COLS) return launch_cols(A, batch, s);
+  if (family == PASS_IMAGE) return launch_image_tiles(A, batch, s);
   if (family == PASS_FIRST) return launch_pass_kind(A, batch, PASS_FIRST, p->cus, s);
   return launch_pass(A, batch, s);
 }
@@ -360,10 +361,15 @@ int run_passes(fbp_plan_s* p, const float* in, float* out, int batch, bool forwa
     } else {
       A.out = out;
       A.out_mode = OUT_IMG_V;
-      e = timed_pass(p, A, batch, FBP_KERNEL_LAST_V, is, cols ? PASS_COLS : PASS_ROWS);
-      if (e == hipSuccess) {
-        A.out_mode = OUT_IMG_H;
-        e = timed_pass(p, A, batch, FBP_KERNEL_LAST_H, is, cols ? PASS_COLS : PASS_ROWS);
+      if (cols && F == 5) {
+        // all four classes over square image tiles: the image is written once
+        e = timed_pass(p, A, batch, FBP_KERNEL_LAST, is, PASS_IMAGE);
+      } else {
+        e = timed_pass(p, A, batch, FBP_KERNEL_LAST_V, is, cols ? PASS_COLS : PASS_ROWS);
+        if (e == hipSuccess) {
+          A.out_mode = OUT_IMG_H;
+          e = timed_pass(p, A, batch, FBP_KERNEL_LAST_H, is, cols ? PASS_COLS : PASS_ROWS);
+        }
       }
     }
     if (e != hipSuccess) return FBP_EDEVICE;

@@ -96,11 +96,13 @@ enum PassKind : int {
   PASS_ROWS = 0,        // full-row tiles, one per block (any mode)
   PASS_FIRST = 1,       // full-row tiles, persistent blocks with the next tile prefetched
   PASS_COLS = 2,        // column tiles with a halo (no filter): OUT_ROWS, OUT_IMG_V, OUT_IMG_H
+  PASS_IMAGE = 3,       // last pass of 5 levels over square image tiles, all four classes
 };
 hipError_t launch_pass_kind(const PassArgs& a, int batch, int kind, int grid, hipStream_t stream);
 template <int L>
 hipError_t launch_first_l(const PassArgs& a, int grid, hipStream_t stream);
 hipError_t launch_cols(const PassArgs& a, int batch, hipStream_t stream);
+hipError_t launch_image_tiles(const PassArgs& a, int batch, hipStream_t stream);
 bool first_pass_supported(const PassArgs& a);
 
 // LDS bytes and threads of a column-tiled pass.

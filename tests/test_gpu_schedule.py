@@ -59,6 +59,31 @@ def test_schedules_are_bit_identical(gpu_lib, N, B, schedules):
         torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("N,B,split", [(256, 3, ([3, 1, 4], 8)), (1024, 2, ([5, 1, 4], 8)),
+                                        (2048, 1, ([2, 4, 1, 4], 8))])
+def test_last_pass_kernels(gpu_lib, N, B, split):
+    """A last pass of 5 levels runs as one launch over 128 x 128 image tiles (all four classes);
+    a last pass of other depth runs split by class pair (two launches).  Same additions in the
+    same order, so the images are bit-identical."""
+    api = gpu_lib
+    P = _lino(N, B, seed=N + 77)
+
+    def run(plan):
+        plan.profile(True)
+        img = api.fbp_reconstruct(plan, P).clone()
+        kinds = plan.profile_read()
+        plan.profile(False)
+        return img, kinds
+
+    with api.fbp_plan(N, B, *_coef()) as plan:
+        ref, kinds = run(plan)
+        assert kinds["last"][1] == 1 and "last_v" not in kinds and "last_h" not in kinds
+        plan.set_schedule(*split)
+        got, kinds = run(plan)
+        assert kinds["last_v"][1] == 1 and kinds["last_h"][1] == 1 and "last" not in kinds
+        assert torch.equal(got, ref)
+
+
 def test_schedule_rejections(gpu_lib):
     api = gpu_lib
     with api.fbp_plan(1024, 1, *_coef()) as plan:

@@ -24,7 +24,8 @@ hipError_t launch_image_tiles(const PassArgs& a, int batch, hipStream_t stream) 
   t.halo = 32;
   t.out_mode = OUT_IMG_V;
   const int tpr = (1 << a.log2n) >> 7;
-  return launch_kernel(fht_image_tile_kernel, t, batch * tpr * tpr, 512, cols_lds_bytes(t), stream);
+  return launch_kernel(fht_image_tile_kernel, t, batch * tpr * tpr, 512,
+                       kTileLdsFloats * sizeof(float), stream);
 }
 
 }  // namespace fhtfbp

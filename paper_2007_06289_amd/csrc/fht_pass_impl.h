@@ -1718,22 +1718,99 @@ __global__ void __launch_bounds__(512) fht_cols_kernel(PassArgs A) {
 }
 
 // ---- last pass over square image tiles -------------------------------------------------------
-// All four classes of the last back-projection pass (2^5 levels to go) in one block, which owns
-// a 128 x 128 image tile: rows y0 .. y0 + 127, columns x0 .. x0 + 127 (eq 20-22).  Classes 0 and
-// 1 reach it through the 4 strips of rows y0 .. y0 + 127, column block x0:
+// All four classes of the last back-projection pass (5 levels to go) in one block, which owns a
+// 128 x 128 image tile: rows y0 .. y0 + 127, columns x0 .. x0 + 127 (eq 20-22).  Classes 0 and 1
+// reach it through the 4 strips of rows y0 .. y0 + 127, column block x0:
 //     image[y][x] = c0[y][x] + c1[y][N-1-x];
 // classes 2 and 3 through the 4 strips of rows x0 .. x0 + 127, column block y0, transposed:
 //     image[y][x] += c2[x][y] + c3[x][N-1-y].
-// Each strip is a column tile of 32 rows by 128 + 32 columns (the halo below), run through the
-// loader's level 0 and levels 1 .. 4 in LDS, and added into accumulators held in registers; the
-// additions are those of the separate V and H launches in the same order, so the results are
-// bit-identical to them.  The image is written once and never read: 16 N^2 bytes in (plus a
-// quarter for the halo) and 4 N^2 out, against 28 N^2 (plus an eighth) for the two launches.
-// Thread t owns rows (t >> 5) + 16 m (m < 8) and columns (t & 31) + 32 b (b < 4) of the tile.
-// One strip of the square-tile pass in registers between its loads and its LDS deposit, so that
-// the next strip's loads are in flight while the current one runs its levels.  Thread t takes
-// row pair m = t >> 5: the float4 at tile column 32 + 4 j (j = t & 31) of both rows, and the
-// halo column j of both rows, for each class of the pair.
+// Each strip is a column tile of 32 rows by 128 + 32 columns (the halo below), run through
+// level 0 in registers and levels 1 .. 4 in LDS, and added into accumulators held in registers;
+// the additions are those of the split V and H kernels in the same order, so the results are
+// bit-identical to them.  The image is written once and never read: 16 N^2 bytes in (plus the
+// halo) and 4 N^2 out, against 28 N^2 (plus the halo) for the two launches.
+//
+// LDS layout: unskewed rows of kTileRs floats after a margin of kTileMargin floats (class c,
+// row i at kTileMargin + (32 c + i) kTileRs).  Columns 0 .. 159 hold the tile; the radix-4
+// stages compute 3 blocks of 61 columns (-3 .. 182) with no clamping: reads below column 0 land
+// in the margin or in the padding of the row before, reads above 159 in the row's own padding,
+// and those values only feed columns outside 32 .. 159, which nothing reads.  The padding also
+// keeps every row 16-byte aligned (float4 deposits).
+constexpr int kTileRs = 188;       // >= 186: written columns -3 .. 182 never reach another row's 0 .. 182
+constexpr int kTileMargin = 64;    // >= 37: the lowest read is column -3 - J - J2 of row 0
+constexpr int kTileLdsFloats = kTileMargin + 64 * kTileRs;
+
+// Two levels (l, l + 1) of a tile in the layout above: the radix-4 form of the column passes
+// (d01 = d23 = -J, e = -J2), two units (four rows of one class) per wave, 3 blocks of 61
+// columns.  Every address is one per-unit base plus an immediate offset.  All reads end at a
+// barrier before any write.
+__device__ __forceinline__ void tile_stage4(float* S, int l) {
+  constexpr int UPW = 2, NB = 3, rs = kTileRs;
+  const int lane = threadIdx.x & 63, wave = wave_id(), waves = blockDim.x >> 6;
+  float* q[UPW];
+  int J[UPW], J2[UPW];
+#pragma unroll
+  for (int k = 0; k < UPW; ++k) {
+    const int unit = wave + k * waves;
+    const int cls = unit >> 3, u = unit & 7;         // 8 units of four rows per class
+    const int pp = u >> l, ib = u & ((1 << l) - 1);
+    const int rb = cls * 32 + (pp << (l + 2)) + ib;
+    J[k] = brev_bits(ib, l);
+    J2[k] = brev_bits(ib, l + 1);
+    q[k] = S + rb * rs + lane - 3;
+  }
+  float o0[UPW * NB], o1[UPW * NB], o2[UPW * NB], o3[UPW * NB];
+#pragma unroll
+  for (int k = 0; k < UPW; ++k) {
+    const float* p0 = q[k];
+    const float* p1 = p0 + (rs << l) - J[k];
+    const float* p2 = p0 + (rs << (l + 1)) - J2[k];
+    const float* p3 = p2 + (rs << l) - J[k];
+#pragma unroll
+    for (int blk = 0; blk < NB; ++blk) {
+      const float a = p0[61 * blk];
+      const float b = p1[61 * blk];
+      const float f = p2[61 * blk];
+      const float g = p3[61 * blk];
+      const float A0 = a + b;
+      const float A1 = a + lanes_shift_up_any(b);
+      const float A2e = f + g;
+      const float A3e = f + lanes_shift_up_any(g);
+      const float t = lanes_shift_up_any(A3e);
+      const int j = k * NB + blk;
+      o0[j] = A0 + A2e;
+      o2[j] = A0 + lanes_shift_up_any(A2e);
+      o1[j] = A1 + t;
+      o3[j] = A1 + lanes_shift_up_any(t);
+    }
+  }
+  __syncthreads();
+  auto put = [&](int k, int blk) {
+    float* p = q[k];
+    const int j = k * NB + blk;
+    p[61 * blk] = o0[j];
+    p[(rs << l) + 61 * blk] = o1[j];
+    p[(rs << (l + 1)) + 61 * blk] = o2[j];
+    p[(rs << (l + 1)) + (rs << l) + 61 * blk] = o3[j];
+  };
+  // blocks above the first: lanes 0 .. 2 repeat the previous block's top columns without their
+  // shifted inputs and are left out (no two lanes write one word, in whatever order the
+  // compiler groups the stores); the first block's lanes 0 .. 2 write into the padding
+  if (lane >= 3) {
+#pragma unroll
+    for (int k = 0; k < UPW; ++k)
+#pragma unroll
+      for (int blk = 1; blk < NB; ++blk) put(k, blk);
+  }
+#pragma unroll
+  for (int k = 0; k < UPW; ++k) put(k, 0);
+  __syncthreads();
+}
+
+// One strip in registers between its loads and its LDS deposit, so that the next strip's loads
+// are in flight while the current one runs its levels.  Thread t takes row pair m = t >> 5: the
+// float4 at tile column 32 + 4 j (j = t & 31) of both rows, and the halo column j of both rows,
+// for each class of the pair.
 struct StripRegs {
   u32x4 a[2], b[2];   // main float4 of rows 2m, 2m + 1
   float pv[2];        // row 2m + 1 one column below the float4 (j = 0 only)
@@ -1764,8 +1841,8 @@ __device__ __forceinline__ void strip_issue(StripRegs& P, const float* c0, size_
 }
 
 // Level 0 on a strip's registers (lower = r0[x] + r1[x], upper = r0[x] + r1[x - 1]; tile column
-// 0 stays as loaded, as in the column loader) and the deposit into skewed LDS rows of stride rs.
-__device__ __forceinline__ void strip_deposit(const StripRegs& P, float* S, int rs) {
+// 0 stays as loaded, as in the column loader) and the deposit into the tile layout.
+__device__ __forceinline__ void strip_deposit(const StripRegs& P, float* S) {
   const int tid = threadIdx.x, m = tid >> 5, j = tid & 31;
 #pragma unroll
   for (int cl = 0; cl < 2; ++cl) {
@@ -1775,31 +1852,24 @@ __device__ __forceinline__ void strip_deposit(const StripRegs& P, float* S, int 
     const float b2 = __uint_as_float(P.b[cl].z), b3 = __uint_as_float(P.b[cl].w);
     const float w = __shfl_up(b3, 1);                 // the previous float4 of row 2m + 1
     const float prev = j == 0 ? P.pv[cl] : w;
-    float* lo = S + (cl * 32 + 2 * m) * rs;
-    float* up = lo + rs;
-    // main: tile columns 32 + 4 j .. 32 + 4 j + 3, skew 1 + j / 8
-    const int lc = 32 + 4 * j + 1 + (j >> 3);
-    lo[lc] = a0 + b0;
-    lo[lc + 1] = a1 + b1;
-    lo[lc + 2] = a2 + b2;
-    lo[lc + 3] = a3 + b3;
-    up[lc] = a0 + prev;
-    up[lc + 1] = a1 + b0;
-    up[lc + 2] = a2 + b1;
-    up[lc + 3] = a3 + b2;
-    // halo: tile column j (skew 0)
+    float* lo = S + kTileMargin + (cl * 32 + 2 * m) * kTileRs;
+    float* up = lo + kTileRs;
+    float4* lo4 = reinterpret_cast<float4*>(__builtin_assume_aligned(lo + 32 + 4 * j, 16));
+    float4* up4 = reinterpret_cast<float4*>(__builtin_assume_aligned(up + 32 + 4 * j, 16));
+    *lo4 = make_float4(a0 + b0, a1 + b1, a2 + b2, a3 + b3);
+    *up4 = make_float4(a0 + prev, a1 + b0, a2 + b1, a3 + b2);
     const float hbm = __shfl_up(P.hb[cl], 1);
     lo[j] = j == 0 ? P.ha[cl] : P.ha[cl] + P.hb[cl];
     up[j] = j == 0 ? P.hb[cl] : P.ha[cl] + hbm;
   }
 }
 
+// Thread t owns rows (t >> 5) + 16 m (m < 8) and columns (t & 31) + 32 k (k < 4) of the tile.
 // At most 128 VGPRs, so that two blocks (16 waves) share a compute unit.
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
 fht_image_tile_kernel(PassArgs A) {
   extern __shared__ float S[];
-  constexpr int F = 5, R = 32, TT = 128, W = 128, H = 32, NS = TT / R;
-  constexpr int wt = W + H, rs = (wt + (wt >> 5) + 1) | 1;
+  constexpr int F = 5, R = 32, TT = 128, W = 128, H = 32, NS = TT / R, rs = kTileRs;
   const int tid = threadIdx.x;
   const int N = 1 << A.log2n;
   const int tpr = N / TT;                            // tiles per image row
@@ -1819,14 +1889,15 @@ fht_image_tile_kernel(PassArgs A) {
   for (int m = 0; m < 8; ++m)
 #pragma unroll
     for (int k = 0; k < 4; ++k) acc[m][k] = 0.f;
-  const float* s0 = S;
-  const float* s1 = S + R * rs;
+  float* T0 = S + kTileMargin;
+  const float* s0 = T0;
+  const float* s1 = T0 + R * rs;
   StripRegs P;
   strip_issue(P, lino, nn, x0, y0, A.log2n);
   for (int ph = 0; ph < 2 * NS; ++ph) {
     const bool hpart = ph >= NS;
     const int s = hpart ? ph - NS : ph;
-    strip_deposit(P, S, rs);
+    strip_deposit(P, S);
     __syncthreads();
     if (ph + 1 < 2 * NS) {
       // the next strip's loads go out now and land during this strip's levels
@@ -1835,11 +1906,9 @@ fht_image_tile_kernel(PassArgs A) {
       const int sn = hn ? pn - NS : pn;
       strip_issue(P, lino + (hn ? 2 : 0) * nn, nn, hn ? y0 : x0, (hn ? x0 : y0) + sn * R, A.log2n);
     }
-    // levels 1 .. 4: two radix-4 stages over 3 blocks of 61 columns, two units per wave
-    cols_stage4<2, 3>(S, rs, F, 1, wt);
-    cols_stage4<2, 3>(S, rs, F, 3, wt);
-    // LDS addresses with the skew written out (c, r < 32 and 16): one base per row and class,
-    // immediate offsets per column
+    // levels 1 .. 4 as two radix-4 stages
+    tile_stage4(T0, 1);
+    tile_stage4(T0, 3);
     if (!hpart) {
       // tile rows 32 s .. 32 s + 31: this thread's rows r and r + 16 of the strip, columns
       // x = c + 32 k: class 0 at H + x, class 1 at H + W - 1 - x
@@ -1849,26 +1918,23 @@ fht_image_tile_kernel(PassArgs A) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           const int rho = brev_bits(r + 16 * h, F);
-          const float* p0 = s0 + rho * rs + (H + 1) + c;            // cat(rho, H + c)
-          const float* p1 = s1 + rho * rs + (H + W + 3) - c;        // cat(rho, H + W - 1 - c)
+          const float* p0 = s0 + rho * rs + H + c;
+          const float* p1 = s1 + rho * rs + (H + W - 1) - c;
 #pragma unroll
-          for (int k = 0; k < 4; ++k) acc[2 * s2 + h][k] += p0[33 * k] + p1[-33 * k];
+          for (int k = 0; k < 4; ++k) acc[2 * s2 + h][k] += p0[32 * k] + p1[-32 * k];
         }
       }
     } else {
       // tile columns 32 s .. 32 s + 31 are strip rows: this thread's column c (strip row c),
       // its rows u = r + 16 m: class 2 at column H + u, class 3 at H + W - 1 - u
       const int rho = brev_bits(c, F);
-      const float* p0 = s0 + rho * rs + (H + 1) + r;                // cat(rho, H + r)
-      const float* p1 = s1 + rho * rs + (H + W + 3) - r;            // cat(rho, H + W - 1 - r)
+      const float* p0 = s0 + rho * rs + H + r;
+      const float* p1 = s1 + rho * rs + (H + W - 1) - r;
 #pragma unroll
       for (int s2 = 0; s2 < NS; ++s2) {
         if (s2 != s) continue;
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
-          const int o = 16 * m + (m >> 1);
-          acc[m][s2] = acc[m][s2] + p0[o] + p1[-o];
-        }
+        for (int m = 0; m < 8; ++m) acc[m][s2] = acc[m][s2] + p0[16 * m] + p1[-16 * m];
       }
     }
     __syncthreads();

@@ -358,6 +358,22 @@ def main():
           f"(events {ev0.elapsed_time(ev1) / args.steps:.3f} ms/step)", file=sys.stderr,
           flush=True)
 
+    # the same batch captured as one HIP graph and replayed (host launch cost out of the
+    # picture); reported beside the eager rate, which stays the headline value
+    graph = F.fbp_graph_create([plan], [lino], [img])
+    graph.launch()
+    torch.cuda.synchronize()
+    g0 = torch.cuda.Event(enable_timing=True)
+    g1 = torch.cuda.Event(enable_timing=True)
+    g0.record()
+    for _ in range(args.steps):
+        graph.launch()
+    g1.record()
+    torch.cuda.synchronize()
+    graph.close()
+    graph_ms = g0.elapsed_time(g1) / args.steps
+    print(f"[bench] graph replay: {graph_ms:.3f} ms/step", file=sys.stderr, flush=True)
+
     levels = plan.passes()
     kernels = {}
     for kind, (tot, cnt) in prof.items():
@@ -396,6 +412,8 @@ def main():
         "roofline": roofline,
         "kernels": {k: {kk: round(vv, 4) if isinstance(vv, float) else vv
                         for kk, vv in v.items()} for k, v in kernels.items()},
+        "graph": {"ms_per_step": round(graph_ms, 4),
+                  "slices_per_s": round(B / (graph_ms * 1e-3), 1)},
         "path": {"algorithmic_bytes_per_slice": 20 * N * N,
                  "GB_per_s": round(path_gbs, 1), "frac_of_peak": round(path_gbs / HBM_PEAK_GBS, 4)},
     }

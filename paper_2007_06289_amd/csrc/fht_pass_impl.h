@@ -23,6 +23,8 @@
 // The butterflies are done in place (lower into the row of pattern 2t, upper into 2t+1), so
 // after F levels sub-strip i sits in physical row bitreverse_F(i).
 #pragma once
+#include <type_traits>
+
 #include "fhtfbp_internal.h"
 
 namespace fhtfbp {
@@ -765,6 +767,16 @@ __device__ __forceinline__ void level_stream_rot(const PassArgs& A, float* S, fl
 // The last stage of the pass (stage4_store) stores its outputs to HBM directly: tile row rho's
 // column x goes to column (x + sig0 + v brev(rho, F)) mod N of output row brev(rho, F) 2^k_lo + v.
 constexpr int kStageMaxBlocks = 9;    // blocks of 61 columns per wave and stage
+constexpr int kStageInnerLast = 7;    // last block index j that stage4_inner_ok covers
+
+// Blocks j = 1 .. 7 of a wave never wrap around the row: with 17 blocks (N = 1024) over two
+// waves per unit they cover columns 61 (first + 2 j) - 3 .. + 60, i.e. 119 .. 975, and every
+// read column c + D (D = 0, d01, e, e + d23) stays in 0 .. 1023 when -119 <= D <= 48.
+__device__ __forceinline__ bool stage4_inner_ok(int nb, int step, int d01, int e, int d23) {
+  const int lo = min(min(0, d01), min(e, e + d23));
+  const int hi = max(max(0, d01), max(e, e + d23));
+  return nb == 17 && step == 2 && lo >= -119 && hi <= 48;
+}
 
 __device__ __forceinline__ int wrap_half(int d, int N) {
   d &= N - 1;
@@ -819,26 +831,36 @@ __device__ __forceinline__ void stage4(const PassArgs& A, float* S, int l, int r
   float* p3 = p2 + (rs << l);
   // blocks past the wave's last repeat it: the same values are computed and stored twice
   float o0[kStageMaxBlocks], o1[kStageMaxBlocks], o2[kStageMaxBlocks], o3[kStageMaxBlocks];
+  // with 17 blocks over two waves per unit (N = 1024), blocks j = 1 .. 7 of a wave lie at
+  // columns 119 .. 975 and none of their reads wraps: they skip the cyclic masks
+  const bool inner_ok = stage4_inner_ok(nb, step, d01, e, d23);
+  auto reads = [&](auto inner_tag) {
+    constexpr bool INNER = decltype(inner_tag)::value;
 #pragma unroll
-  for (int j = 0; j < kStageMaxBlocks; ++j) {
-    const int blk = min(first + j * step, nb - 1);
-    const int c = blk * 61 - 3 + lane;
-    const int x0 = c & mask, x1 = (c + d01) & mask, x2 = (c + e) & mask;
-    const int x3 = (c + e + d23) & mask;
-    const float a = p0[IN_SKEW ? x0 + (x0 >> 5) : x0];
-    const float b = p1[IN_SKEW ? x1 + (x1 >> 5) : x1];
-    const float f = p2[IN_SKEW ? x2 + (x2 >> 5) : x2];
-    const float g = p3[IN_SKEW ? x3 + (x3 >> 5) : x3];
-    const float A0 = a + b;
-    const float A1 = a + lanes_shift_up_any(b);
-    const float A2e = f + g;
-    const float A3e = f + lanes_shift_up_any(g);
-    const float t = lanes_shift_up_any(A3e);
-    o0[j] = A0 + A2e;
-    o2[j] = A0 + lanes_shift_up_any(A2e);
-    o1[j] = A1 + t;
-    o3[j] = A1 + lanes_shift_up_any(t);
-  }
+    for (int j = 0; j < kStageMaxBlocks; ++j) {
+      const bool inner = INNER && j >= 1 && j <= kStageInnerLast;
+      const int blk = inner ? first + j * step : min(first + j * step, nb - 1);
+      const int c = blk * 61 - 3 + lane;
+      const int x0 = inner ? c : c & mask, x1 = inner ? c + d01 : (c + d01) & mask;
+      const int x2 = inner ? c + e : (c + e) & mask;
+      const int x3 = inner ? c + e + d23 : (c + e + d23) & mask;
+      const float a = p0[IN_SKEW ? x0 + (x0 >> 5) : x0];
+      const float b = p1[IN_SKEW ? x1 + (x1 >> 5) : x1];
+      const float f = p2[IN_SKEW ? x2 + (x2 >> 5) : x2];
+      const float g = p3[IN_SKEW ? x3 + (x3 >> 5) : x3];
+      const float A0 = a + b;
+      const float A1 = a + lanes_shift_up_any(b);
+      const float A2e = f + g;
+      const float A3e = f + lanes_shift_up_any(g);
+      const float t = lanes_shift_up_any(A3e);
+      o0[j] = A0 + A2e;
+      o2[j] = A0 + lanes_shift_up_any(A2e);
+      o1[j] = A1 + t;
+      o3[j] = A1 + lanes_shift_up_any(t);
+    }
+  };
+  if (inner_ok) reads(std::true_type{});
+  else reads(std::false_type{});
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < kStageMaxBlocks; ++j) {
@@ -901,17 +923,36 @@ __device__ __forceinline__ void stage4_store(const PassArgs& A, const float* S, 
   const int y0 = (sig0 + v * i0) * 4, y1 = (sig0 + v * i1) * 4;
   const int y2 = (sig0 + v * i2) * 4, y3 = (sig0 + v * i3) * 4;
   const int nbw = (nb - first + step - 1) / step;   // this wave's blocks
+  // as in stage4, blocks j = 1 .. 7 never wrap when there are 17 blocks over two waves; on
+  // unskewed rows they then read through one base per row with immediate offsets
+  const bool inner_ok = !IN_SKEW && stage4_inner_ok(nb, step, d01, e, d23);
+  const int cb = first * 61 - 3 + lane;             // column of block j = 0
+  const float* q0 = p0 + cb;
+  const float* q1 = p1 + (cb + d01);
+  const float* q2 = p2 + (cb + e);
+  const float* q3 = p3 + (cb + e + d23);
+  auto blocks = [&](auto inner_tag) {
+    constexpr bool INNER = decltype(inner_tag)::value;
 #pragma unroll
   for (int j = 0; j < kStageMaxBlocks; ++j) {
     if (j < nbw) {
+      const bool inner = INNER && j >= 1 && j <= kStageInnerLast;
       const int blk = first + j * step;
       const int c = blk * 61 - 3 + lane;
-      const int x0 = c & mask, x1 = (c + d01) & mask, x2 = (c + e) & mask;
-      const int x3 = (c + e + d23) & mask;
-      const float a = p0[IN_SKEW ? x0 + (x0 >> 5) : x0];
-      const float b = p1[IN_SKEW ? x1 + (x1 >> 5) : x1];
-      const float f = p2[IN_SKEW ? x2 + (x2 >> 5) : x2];
-      const float g = p3[IN_SKEW ? x3 + (x3 >> 5) : x3];
+      float a, b, f, g;
+      if (inner) {
+        a = q0[122 * j];
+        b = q1[122 * j];
+        f = q2[122 * j];
+        g = q3[122 * j];
+      } else {
+        const int x0 = c & mask, x1 = (c + d01) & mask, x2 = (c + e) & mask;
+        const int x3 = (c + e + d23) & mask;
+        a = p0[IN_SKEW ? x0 + (x0 >> 5) : x0];
+        b = p1[IN_SKEW ? x1 + (x1 >> 5) : x1];
+        f = p2[IN_SKEW ? x2 + (x2 >> 5) : x2];
+        g = p3[IN_SKEW ? x3 + (x3 >> 5) : x3];
+      }
       const float A0 = a + b;
       const float A1 = a + lanes_shift_up_any(b);
       const float A2e = f + g;
@@ -930,6 +971,9 @@ __device__ __forceinline__ void stage4_store(const PassArgs& A, const float* S, 
       }
     }
   }
+  };
+  if (inner_ok) blocks(std::true_type{});
+  else blocks(std::false_type{});
 }
 
 // Two-phase form for rows shorter than 64 columns: every thread reads all its butterfly inputs,

@@ -237,7 +237,9 @@ int fbp_plan_passes(fbp_plan_t plan, int32_t* levels, int32_t cap);
  * the filter, holds 2^levels[0] full rows in LDS (levels[0] <= first_max of
  * fbp_plan_schedule_info, else FBP_ERANGE).  For N >= 256 the later passes work on tiles of
  * 2^levels[i] rows by 2^log2w columns plus a halo; 6 <= log2w <= min(10, log2 N), 0 keeps the
- * current width, and a tile that does not fit the LDS gives FBP_ERANGE.  Below N = 256 every
+ * current width, and a tile that does not fit the LDS gives FBP_ERANGE.  A last pass of 5
+ * levels runs over 128 x 128 image tiles whatever the width (the width still applies to the
+ * middle passes and to a last pass of other depth).  Below N = 256 every
  * pass holds full rows.  fht_forward keeps the plan's initial schedule.  When the new schedule
  * needs more scratch than the plan holds, the call synchronises the plan's stream and
  * allocates it (FBP_ENOMEM on failure, the schedule unchanged).  Graphs captured before the

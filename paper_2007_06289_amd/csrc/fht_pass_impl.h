@@ -800,7 +800,7 @@ __device__ __forceinline__ bool stage4_fits(const PassArgs& A) {
 // IN_SKEW: the stage reads skewed rows (from the filter or a streaming level); later stages
 // read the unskewed rows an earlier stage wrote.  The stage writes its rows unskewed, at their
 // frame positions (the last stage of a pass is stage4_store).
-template <bool ROT, bool IN_SKEW>
+template <bool ROT, bool IN_SKEW, bool INNER_OK = true>
 __device__ __forceinline__ void stage4(const PassArgs& A, float* S, int l, int row0) {
   const int N = 1 << A.log2n, mask = N - 1;
   const int lane = threadIdx.x & 63, wave = wave_id();
@@ -833,7 +833,7 @@ __device__ __forceinline__ void stage4(const PassArgs& A, float* S, int l, int r
   float o0[kStageMaxBlocks], o1[kStageMaxBlocks], o2[kStageMaxBlocks], o3[kStageMaxBlocks];
   // with 17 blocks over two waves per unit (N = 1024), blocks j = 1 .. 7 of a wave lie at
   // columns 119 .. 975 and none of their reads wraps: they skip the cyclic masks
-  const bool inner_ok = stage4_inner_ok(nb, step, d01, e, d23);
+  const bool inner_ok = INNER_OK && stage4_inner_ok(nb, step, d01, e, d23);
   auto reads = [&](auto inner_tag) {
     constexpr bool INNER = decltype(inner_tag)::value;
 #pragma unroll
@@ -859,8 +859,12 @@ __device__ __forceinline__ void stage4(const PassArgs& A, float* S, int l, int r
       o3[j] = A1 + lanes_shift_up_any(t);
     }
   };
-  if (inner_ok) reads(std::true_type{});
-  else reads(std::false_type{});
+  if constexpr (INNER_OK) {
+    if (inner_ok) reads(std::true_type{});
+    else reads(std::false_type{});
+  } else {
+    reads(std::false_type{});
+  }
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < kStageMaxBlocks; ++j) {
@@ -881,7 +885,7 @@ __device__ __forceinline__ void stage4(const PassArgs& A, float* S, int l, int r
 // lane and row, as soon as they are computed.  Nothing is written back to LDS, so the stage
 // needs no barrier between its reads and its stores (the caller's end-of-tile barrier guards
 // the reuse of LDS), and there is no separate write-out.
-template <bool ROT, bool IN_SKEW>
+template <bool ROT, bool IN_SKEW, bool INNER_OK = true>
 __device__ __forceinline__ void stage4_store(const PassArgs& A, const float* S, int l, int row0,
                                              int sig0, int v, float* dst, int k_lo) {
   const int N = 1 << A.log2n, mask = N - 1;
@@ -925,7 +929,7 @@ __device__ __forceinline__ void stage4_store(const PassArgs& A, const float* S, 
   const int nbw = (nb - first + step - 1) / step;   // this wave's blocks
   // as in stage4, blocks j = 1 .. 7 never wrap when there are 17 blocks over two waves; on
   // unskewed rows they then read through one base per row with immediate offsets
-  const bool inner_ok = !IN_SKEW && stage4_inner_ok(nb, step, d01, e, d23);
+  const bool inner_ok = INNER_OK && !IN_SKEW && stage4_inner_ok(nb, step, d01, e, d23);
   const int cb = first * 61 - 3 + lane;             // column of block j = 0
   const float* q0 = p0 + cb;
   const float* q1 = p1 + (cb + d01);
@@ -972,8 +976,12 @@ __device__ __forceinline__ void stage4_store(const PassArgs& A, const float* S, 
     }
   }
   };
-  if (inner_ok) blocks(std::true_type{});
-  else blocks(std::false_type{});
+  if constexpr (INNER_OK && !IN_SKEW) {
+    if (inner_ok) blocks(std::true_type{});
+    else blocks(std::false_type{});
+  } else {
+    blocks(std::false_type{});
+  }
 }
 
 // Two-phase form for rows shorter than 64 columns: every thread reads all its butterfly inputs,
@@ -1279,6 +1287,8 @@ __global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
     const int sig0 = (K > 0) ? window_start_of(row0, A.log2n, A.windowed) : 0;
     // levels: an odd one streams, the rest go two at a time; the last pair stores the tile
     bool stored = false;     // the last stage stored the tile to HBM itself
+    // the unmasked interior blocks add code that higher orders pay for in spilled registers
+    constexpr bool kInner = K <= 2;
     {
       float* copy = S + (1 << A.log2r) * A.rs;
       int l = level0 ? 1 : 0;
@@ -1293,12 +1303,14 @@ __global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
       for (bool first_stage = true; l < F; l += 2, first_stage = false) {
         if (l + 2 == F) {
           float* dst = A.out + (size_t)bq * N * N;
-          if (first_stage) stage4_store<(K > 0), true>(A, S, l, row0, sig0, v, dst, k_lo);
-          else stage4_store<(K > 0), false>(A, S, l, row0, sig0, v, dst, k_lo);
+          if (first_stage)
+            stage4_store<(K > 0), true, kInner>(A, S, l, row0, sig0, v, dst, k_lo);
+          else
+            stage4_store<(K > 0), false, kInner>(A, S, l, row0, sig0, v, dst, k_lo);
           stored = true;
         } else {
-          if (first_stage) stage4<(K > 0), true>(A, S, l, row0);
-          else stage4<(K > 0), false>(A, S, l, row0);
+          if (first_stage) stage4<(K > 0), true, kInner>(A, S, l, row0);
+          else stage4<(K > 0), false, kInner>(A, S, l, row0);
         }
       }
     }

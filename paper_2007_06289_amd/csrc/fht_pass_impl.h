@@ -251,9 +251,10 @@ __device__ void filter_tile(const PassArgs& A, float* S, int q, int row0) {
 // which do not wait behind the vector loads of the next tile that are already in flight.
 // `step_hook(s)` runs at the top of recursion step s (the caller uses it to issue the next
 // tile's loads a few at a time, so the texture unit takes them while the ALUs work).
-template <int K, typename Hook>
-__device__ bool filter_tile_aligned(const PassArgs& A, float* S, int q, int row0, float ct,
-                                    Hook&& step_hook) {
+// WIDE: rows of 128 chunks over two waves (the row length 4096); otherwise C <= 64.
+template <int K, bool WIDE, typename Hook>
+__device__ bool filter_tile_aligned(const PassArgs& A, float* S, float* xs, int q, int row0,
+                                    float ct, Hook&& step_hook) {
   constexpr int L = 32;
   int tid = threadIdx.x;
   asm volatile("" : "+v"(tid));
@@ -342,13 +343,17 @@ __device__ bool filter_tile_aligned(const PassArgs& A, float* S, int q, int row0
       tc[k] = stc[k];
       ta[k] = sta[k];
     }
-    for (int jj = 0; (1 << jj) < C; ++jj) {
+    // a row's chunks span W = min(C, 64) lanes of one wave (C = 128: two waves, the last scan
+    // level below goes across them)
+    const int W = WIDE ? 64 : C;
+    const int cw = c & (W - 1);
+    for (int jj = 0; (1 << jj) < W; ++jj) {
       const int d = 1 << jj;
       float uc[K], ua[K];
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        uc[k] = __shfl_up(tc[k], d, C);
-        ua[k] = __shfl_down(ta[k], d, C);
+        uc[k] = __shfl_up(tc[k], d, W);
+        ua[k] = __shfl_down(ta[k], d, W);
       }
       cfloat* P = phi + jj * K * K;
       float nc[K], na[K];
@@ -365,16 +370,55 @@ __device__ bool filter_tile_aligned(const PassArgs& A, float* S, int q, int row0
       }
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        tc[k] = (c >= d) ? nc[k] : tc[k];
-        ta[k] = (c + d < C) ? na[k] : ta[k];
+        tc[k] = (cw >= d) ? nc[k] : tc[k];
+        ta[k] = (cw + d < W) ? na[k] : ta[k];
+      }
+    }
+    // C = 128: scan level 6 (64 chunks) goes between the row's two waves through LDS.  The
+    // first wave's causal states and the second's anticausal ones are already final; each
+    // wave publishes those, and takes its partner lane's (for the level) and the partner
+    // wave's edge lane (for the shift by one chunk below).
+    float ec[K], ea[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      ec[k] = 0.f;
+      ea[k] = 0.f;
+    }
+    if constexpr (WIDE) {
+      const int half = c >> 6, lane = c & 63;
+      float* mine = xs + ((r * 2 + half) * K) * 64;
+      const float* other = xs + ((r * 2 + (half ^ 1)) * K) * 64;
+#pragma unroll
+      for (int k = 0; k < K; ++k) mine[k * 64 + lane] = half == 0 ? tc[k] : ta[k];
+      __syncthreads();
+      float pk[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        pk[k] = other[k * 64 + lane];
+        ec[k] = other[k * 64 + 63];     // first wave's last chunk (used by the second wave)
+        ea[k] = other[k * 64];          // second wave's first chunk (used by the first wave)
+      }
+      cfloat* P = phi + 6 * K * K;
+      float nv[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        float acc = half == 0 ? ta[k] : tc[k];
+#pragma unroll
+        for (int m = 0; m < K; ++m) acc = fmaf(P[k * K + m], pk[m], acc);
+        nv[k] = acc;
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (half == 0) ta[k] = nv[k];
+        else tc[k] = nv[k];
       }
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const float pc = (C > 1) ? __shfl_up(tc[k], 1, C) : 0.f;
-      const float pa = (C > 1) ? __shfl_down(ta[k], 1, C) : 0.f;
-      stc[k] = (c == 0) ? 0.f : pc;
-      sta[k] = (c == C - 1) ? 0.f : pa;
+      const float pc = (W > 1) ? __shfl_up(tc[k], 1, W) : 0.f;
+      const float pa = (W > 1) ? __shfl_down(ta[k], 1, W) : 0.f;
+      stc[k] = (c == 0) ? 0.f : (cw == 0 ? ec[k] : pc);
+      sta[k] = (c == C - 1) ? 0.f : (cw == W - 1 ? ea[k] : pa);
     }
     // carry correction: the carried-in state through the homogeneous response, oldest first
     // (the table goes through scalar registers 8 steps at a time: the barriers keep the
@@ -1185,7 +1229,7 @@ __device__ __forceinline__ float4 load4_rotated(const float* row, int x, int o, 
 // the second half goes out before the levels; levels 1 .. F - 1 run as radix-4 stages (an odd
 // one streams first), the last of which stores the tile to HBM itself.  The loads of the next
 // tile are in flight through all of it.
-template <int L, int K, int NBLK>
+template <int L, int K, int NBLK, bool WIDE = false>
 __global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
   extern __shared__ float S[];
   const int T = blockDim.x, tid = threadIdx.x;
@@ -1248,11 +1292,10 @@ __global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
     if constexpr (K > 0) {
       // a wave holds 64 / C consecutive rows (at most 8 here): read their factors with scalar
       // loads and let each lane pick its row's
-      const int rpw = 64 >> A.log2c;
       const int wave = __builtin_amdgcn_readfirstlane(ltid >> 6);
       // all eight factors in one go (the table has spare floats past row N - 1), no waits in
-      // between; lanes pick their row's
-      cfloat* sc = as_constant(A.scale + row0 + wave * rpw);
+      // between; lanes pick their row's (C = 128: a wave holds half of row wave / 2)
+      cfloat* sc = as_constant(A.scale + row0 + ((wave << 6) >> A.log2c));
       const int lr = (ltid & 63) >> A.log2c;
       float f8[8];
 #pragma unroll
@@ -1273,11 +1316,14 @@ __global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
     __syncthreads();
     const bool more = tl + (int)gridDim.x < A.total_tiles;
     bool level0 = false;
+    // the scan's exchange area (rows of more than 64 chunks) after the tile and the streaming
+    // copies
+    float* xs = S + (pass_lds_bytes(A) >> 2);
     if constexpr (K > 0) {
       // the first half of the next tile's loads, one every 8 recursion steps (the last tile
       // of a block reloads itself instead of branching: no branch splits the filter's code)
       const int tn = more ? tl + (int)gridDim.x : tl;
-      level0 = filter_tile_aligned<K>(A, S, q, row0, ct, [&](int s) {
+      level0 = filter_tile_aligned<K, WIDE>(A, S, xs, q, row0, ct, [&](int s) {
         if ((s & 7) == 0) issue_one(tn, s >> 3);
       });
     } else {
@@ -2044,7 +2090,19 @@ hipError_t launch_lk(const PassArgs& a, int batch, hipStream_t stream) {
 template <int L, int NBLK>
 hipError_t launch_first_ln(const PassArgs& a, int grid, hipStream_t stream) {
   const int threads = (1 << a.log2r) << a.log2c;
-  const size_t lds = pass_lds_bytes(a);
+  const size_t lds = pass_lds_bytes(a) + first_xchg_floats(a) * sizeof(float);
+  if (a.log2c > 6) {
+    // rows of 128 chunks (N = 4096) over two waves: 16 blocks per unit, orders up to 2
+    if constexpr (NBLK == 16) {
+      switch (a.order) {
+        case 0: return launch_kernel(fht_first_kernel<L, 0, 16, true>, a, grid, threads, lds, stream);
+        case 1: return launch_kernel(fht_first_kernel<L, 1, 16, true>, a, grid, threads, lds, stream);
+        case 2: return launch_kernel(fht_first_kernel<L, 2, 16, true>, a, grid, threads, lds, stream);
+        default: break;
+      }
+    }
+    return hipErrorInvalidValue;
+  }
   switch (a.order) {
     case 0: return launch_kernel(fht_first_kernel<L, 0, NBLK>, a, grid, threads, lds, stream);
     case 1: return launch_kernel(fht_first_kernel<L, 1, NBLK>, a, grid, threads, lds, stream);

@@ -30,6 +30,10 @@ struct fbp_plan_s {
   std::vector<double> b, a;   // host copies [groups][order]
   int coef_stride = 0;
   float* d_coef = nullptr;
+  // N = 4096: the filter's own chunks are 64 samples (C = 64), while the persistent first pass
+  // runs 32-sample chunks over two waves per row (C = 128), with a table of its own
+  float* d_coef32 = nullptr;
+  int coef_stride32 = 0;
   float* d_scale = nullptr;
   int* d_sigma = nullptr;
   float* d_scratch[2] = {nullptr, nullptr};
@@ -153,11 +157,12 @@ std::vector<int> backprojection_levels(int n, int fmax) {
   return v;
 }
 
-int upload_coefficients(fbp_plan_s* p) {
+// One coefficient table for chunks of L samples: per group b[K], a[K], Phi^(L 2^j) for
+// j < kScanLevels, and the homogeneous responses h_k[0 .. L-1].
+int fill_coefficients(const fbp_plan_s* p, int L, int stride, std::vector<float>& host) {
   const int K0 = p->order, G = p->groups;
   const int K = kernel_order(K0);   // taps K0..K-1 are zero
-  const int L = 1 << p->log2l;
-  std::vector<float> host((size_t)G * p->coef_stride, 0.f);
+  host.assign((size_t)G * stride, 0.f);
   std::vector<double> phi(kScanLevels * K * K), hom((size_t)K * L);
   for (int g = 0; g < G; ++g) {
     std::vector<double> bg(K, 0.0), ag(K, 0.0);
@@ -168,19 +173,30 @@ int upload_coefficients(fbp_plan_s* p) {
     if (!stable(ag.data(), K0)) return FBP_EUNSTABLE;
     for (int k = 0; k < K; ++k) {
       if (!isfinite(bg[k])) return FBP_EUNSTABLE;
-      host[(size_t)g * p->coef_stride + k] = (float)bg[k];
-      host[(size_t)g * p->coef_stride + K + k] = (float)ag[k];
+      host[(size_t)g * stride + k] = (float)bg[k];
+      host[(size_t)g * stride + K + k] = (float)ag[k];
     }
     transition_powers(ag.data(), K, L, phi.data());
     for (int i = 0; i < kScanLevels * K * K; ++i)
-      host[(size_t)g * p->coef_stride + 2 * K + i] = (float)phi[i];
+      host[(size_t)g * stride + 2 * K + i] = (float)phi[i];
     homogeneous_table(ag.data(), K, L, hom.data());
     for (int i = 0; i < K * L; ++i)
-      host[(size_t)g * p->coef_stride + 2 * K + kScanLevels * K * K + i] = (float)hom[i];
+      host[(size_t)g * stride + 2 * K + kScanLevels * K * K + i] = (float)hom[i];
   }
+  return FBP_OK;
+}
+
+int upload_coefficients(fbp_plan_s* p) {
+  std::vector<float> host, host32;
+  int rc = fill_coefficients(p, 1 << p->log2l, p->coef_stride, host);
+  if (rc == FBP_OK && p->d_coef32) rc = fill_coefficients(p, 32, p->coef_stride32, host32);
+  if (rc != FBP_OK) return rc;
   if (hipStreamSynchronize(p->stream) != hipSuccess) return FBP_EDEVICE;
   if (hipMemcpy(p->d_coef, host.data(), host.size() * sizeof(float), hipMemcpyHostToDevice) !=
       hipSuccess)
+    return FBP_EDEVICE;
+  if (p->d_coef32 && hipMemcpy(p->d_coef32, host32.data(), host32.size() * sizeof(float),
+                               hipMemcpyHostToDevice) != hipSuccess)
     return FBP_EDEVICE;
   return FBP_OK;
 }
@@ -231,6 +247,7 @@ void free_plan(fbp_plan_s* p) {
   clear_recs(p);
   hipFree(p->d_partial);
   hipFree(p->d_coef);
+  hipFree(p->d_coef32);
   hipFree(p->d_scale);
   hipFree(p->d_sigma);
   hipFree(p->d_scratch[0]);
@@ -313,6 +330,26 @@ PassArgs base_args(const fbp_plan_s* p) {
   return A;
 }
 
+// Whether pass 0 of a back projection can run on the persistent first-pass kernel, which needs
+// 32-sample chunks.  At N = 4096 the plan's filter chunks are 64 samples; pass 0 then switches
+// to 32-sample chunks over two waves per row (its own coefficient table and LDS row stride).
+// A keeps the plan's values when the answer is no.
+bool first_pass_args(const fbp_plan_s* p, PassArgs& A) {
+  PassArgs F = A;
+  if (p->log2l != 5) {
+    if (!p->d_coef32) return false;
+    F.log2l = 5;
+    F.log2c = p->log2n - 5;
+    F.rs = p->n + (p->n >> 5);
+    F.coef = p->d_coef32;
+    F.coef_stride = p->coef_stride32;
+  }
+  const size_t lds = pass_lds_bytes(F) + first_xchg_floats(F) * sizeof(float);
+  if (!pass_streams(F) || !first_pass_supported(F) || lds > (size_t)kLdsBudget) return false;
+  A = F;
+  return true;
+}
+
 // Run the transposed FHT passes.  forward: image -> linogram through the mirrored transform;
 // otherwise linogram -> image (with the filter fused into the first pass when `filter`).
 int run_passes(fbp_plan_s* p, const float* in, float* out, int batch, bool forward,
@@ -346,8 +383,7 @@ int run_passes(fbp_plan_s* p, const float* in, float* out, int batch, bool forwa
       A.out_mode = OUT_ROWS;
       if (cols) {
         e = timed_pass(p, A, batch, kind, is, PASS_COLS);
-      } else if (first && !forward && p->log2l == 5 && pass_streams(A) &&
-                 first_pass_supported(A)) {
+      } else if (first && !forward && first_pass_args(p, A)) {
         A.total_tiles = batch * 4 * (p->n >> F);
         e = timed_pass(p, A, batch, kind, is, PASS_FIRST);
       } else {
@@ -389,9 +425,13 @@ bool first_pass_supported(const PassArgs& a) {
   const int nblk = ((1 << a.log2n) / segs) >> 6;
   // the filter reads a wave's coefficients once for all its rows: the rows of a wave
   // (64 / C of them) must lie in one angle group (4N / groups consecutive rows)
-  const int rows_per_wave = 64 >> a.log2c;
+  const int rows_per_wave = std::max(1, 64 >> a.log2c);   // C = 128: half a row per wave
   const int rows_per_group = (4 << a.log2n) / std::max(1, a.groups);
-  if (a.order > 0 && (rows_per_wave < 1 || rows_per_group % rows_per_wave != 0)) return false;
+  if (a.order > 0 && (rows_per_group < 1 || rows_per_group % rows_per_wave != 0)) return false;
+  // rows over two waves: orders up to 2 (at N = 4096 the reconstruction amplifies the
+  // zero-frequency rounding of the scan tables by ~N; with 32-sample chunks, order 4 missed the
+  // float32 bar there, so higher orders keep the 64-sample chunks of the generic kernel)
+  if (a.log2c > 6 && (a.log2c > 7 || a.order > 2 || threads > 1024 || nblk != 16)) return false;
   return nblk == 4 || nblk == 8 || nblk == 16;
 }
 
@@ -401,7 +441,7 @@ hipError_t launch_pass_kind(const PassArgs& a, int batch, int kind, int cus, hip
   (void)kind;
   if (a.log2l != 5) return hipErrorInvalidValue;
   const int threads = (1 << a.log2r) << a.log2c;
-  const size_t lds = pass_lds_bytes(a);
+  const size_t lds = pass_lds_bytes(a) + first_xchg_floats(a) * sizeof(float);
   int per_cu = (int)(kLdsBudget / std::max<size_t>(lds, 1));
   per_cu = std::max(1, std::min(per_cu, 2048 / threads));
   const int grid = std::min(a.total_tiles, cus * per_cu);
@@ -652,6 +692,8 @@ int fbp_plan(const fbp_plan_desc* d, fbp_plan_t* out) {
   {
     const int KK = kernel_order(K);
     p->coef_stride = 2 * KK + kScanLevels * KK * KK + KK * (1 << p->log2l);
+    // rows of more than 64 chunks of 32 (N = 4096): a second table for the first pass
+    if (p->log2n > 11) p->coef_stride32 = 2 * KK + kScanLevels * KK * KK + KK * 32;
   }
 
   // per-row tables: c_t = k_t w_t (times k_t again for FHT-normalised input), window starts
@@ -676,6 +718,9 @@ int fbp_plan(const fbp_plan_desc* d, fbp_plan_t* out) {
   p->scratch_floats = (size_t)p->max_batch * 4 * per_class;
   const int nscratch = scratch_needed(std::max(p->levels.size(), p->fwd_levels.size()));
   bool ok = hipMalloc(&p->d_coef, (size_t)G * p->coef_stride * sizeof(float)) == hipSuccess &&
+            (p->coef_stride32 == 0 ||
+             hipMalloc(&p->d_coef32, (size_t)G * p->coef_stride32 * sizeof(float)) ==
+                 hipSuccess) &&
             hipMalloc(&p->d_scale, (N + kScalePad) * sizeof(float)) == hipSuccess &&
             hipMalloc(&p->d_sigma, N * sizeof(int)) == hipSuccess;
   for (int i = 0; ok && i < nscratch; ++i)

@@ -8,7 +8,7 @@ namespace fhtfbp {
 
 constexpr int kMaxOrder = 8;       // largest recursive-filter order supported
 constexpr int kScalePad = 8;       // the row-factor table has 8 spare floats (whole-block scalar loads)
-constexpr int kScanLevels = 6;     // chunk transition matrices Phi^(L 2^j), j < 6 (C <= 64)
+constexpr int kScanLevels = 7;     // chunk transition matrices Phi^(L 2^j), j < 7 (C <= 128)
 constexpr int kMaxPasses = 12;
 constexpr int kLdsBudget = 160 * 1024;
 
@@ -77,18 +77,25 @@ hipError_t launch_pass_l(const PassArgs& a, int batch, hipStream_t stream);
 inline int kernel_order(int K) { return K <= 4 ? K : kMaxOrder; }
 
 // Whether a pass runs its levels in the streaming form (rows of >= 64 columns, whole waves).
-inline bool pass_streams(const PassArgs& a) {
+__host__ __device__ inline bool pass_streams(const PassArgs& a) {
   const int threads = (1 << a.log2r) << a.log2c;
   return a.levels > 0 && a.log2n >= 6 && (threads & 63) == 0;
 }
 
 // LDS bytes of a pass: the tile of 2^log2r skewed rows, plus 64 floats per streaming unit.
-inline size_t pass_lds_bytes(const PassArgs& a) {
+__host__ __device__ inline size_t pass_lds_bytes(const PassArgs& a) {
   const size_t tile = (size_t)(1 << a.log2r) * a.rs * sizeof(float);
   if (!pass_streams(a)) return tile;
   const int threads = (1 << a.log2r) << a.log2c;
   const int waves = threads >> 6, pairs = 1 << (a.log2r - 1);
   return tile + (size_t)(waves > pairs ? waves : pairs) * 64 * sizeof(float);
+}
+
+// The persistent first pass with more than 64 chunks per row (a row over two waves) exchanges
+// the chunk scan's end states between the row's waves through LDS: per row, 2 x 64 lanes x K
+// floats after the pass's other LDS.
+__host__ __device__ inline size_t first_xchg_floats(const PassArgs& a) {
+  return a.log2c > 6 ? (size_t)(1 << a.log2r) * 128 * a.order : 0;
 }
 
 // Kernel families a pass can run on.

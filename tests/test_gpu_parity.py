@@ -166,6 +166,27 @@ def test_reconstruct_matches_oracle(gpu_lib, N, B, order):
     assert _rel_rmse(got, ref) < RTOL_RMSE
 
 
+def test_reconstruct_4096_rows_over_two_waves(gpu_lib):
+    """N = 4096: a row has 128 chunks of 32 samples, so pass 0 spreads each row over two waves
+    and carries the chunk scan's last level between them through LDS (orders up to 2; the
+    filter alone keeps 64-sample chunks).  Against the FP64 oracle, both fused and as the
+    filter followed by the back projection, which takes the other chunking."""
+    api = gpu_lib
+    N = 4096
+    ells = I.random_ellipses(N, 10, 4096, disc=0.34, batch=1)
+    P = I.linogram(ells, N, device="cuda", dtype=torch.float32)
+    Pd = P.cpu().to(torch.float64)
+    for order in (1, 2):
+        b, a = _coef(order)
+        with api.fbp_plan(N, 1, b, a) as plan:
+            got = api.fbp_reconstruct(plan, P).clone()
+            two_step = api.fht_backproject(plan, api.fbp_filter(plan, P))
+            torch.cuda.synchronize()
+        ref = O.fbp_fht(Pd, torch.tensor(b), torch.tensor(a))
+        assert _rel_rmse(got, ref) < RTOL_RMSE, order
+        assert _rel_rmse(two_step, ref) < RTOL_RMSE, order
+
+
 @pytest.mark.parametrize("N,flags", [(512, 4), (1024, 4), (1024, 1), (1024, 2)])
 def test_reconstruct_flags_on_the_fused_first_pass(gpu_lib, N, flags):
     """The fused first pass (filter, level 0 in registers, radix-4 stages, direct stores) with

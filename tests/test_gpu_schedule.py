@@ -38,6 +38,7 @@ def _rel(got, ref):
     (256, 2, [[4, 4, 0], [2, 6, 7], [4, 4, 7], [4, 4, 6], [3, 3, 2, 8], [1, 1, 6, 7]]),
     (1024, 2, [[5, 5, 7], [5, 5, 9], [4, 6, 7], [3, 3, 4, 8], [2, 4, 4, 8], [5, 1, 4, 8]]),
     (2048, 1, [[4, 4, 3, 8], [3, 5, 3, 8], [4, 3, 4, 9], [2, 3, 3, 3, 8]]),
+    (4096, 1, [[3, 4, 5, 8], [1, 6, 5, 8], [3, 5, 4, 8], [2, 5, 5, 9]]),
 ])
 def test_schedules_are_bit_identical(gpu_lib, N, B, schedules):
     """Every listed schedule is one the kernels can run (last entry: log2 of the column-tile

@@ -374,10 +374,14 @@ __device__ bool filter_tile_aligned(const PassArgs& A, float* S, float* xs, int 
         ta[k] = (cw + d < W) ? na[k] : ta[k];
       }
     }
-    // C = 128: scan level 6 (64 chunks) goes between the row's two waves through LDS.  The
-    // first wave's causal states and the second's anticausal ones are already final; each
-    // wave publishes those, and takes its partner lane's (for the level) and the partner
-    // wave's edge lane (for the shift by one chunk below).
+    // C = 128: the row's two waves join through LDS.  After the levels above, lane i of the
+    // second wave holds the causal state of its chunks 64 .. 64 + i alone, and lane i of the
+    // first the anticausal state of its chunks i .. 63 alone.  The first wave's causal state at
+    // chunk 63 (S) and the second's anticausal state at chunk 64 (T) are complete; each wave
+    // publishes its own, and every lane adds the other's carried over its distance m in
+    // chunks: Phi^(32 m) S with m = i + 1 in the second wave, Phi^(32 m) T with m = 64 - i in
+    // the first, the power taken from the table's Phi^(32 2^j) by the bits of m.  S and T are
+    // also the carries across the wave boundary in the shift by one chunk below.
     float ec[K], ea[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -391,26 +395,34 @@ __device__ bool filter_tile_aligned(const PassArgs& A, float* S, float* xs, int 
 #pragma unroll
       for (int k = 0; k < K; ++k) mine[k * 64 + lane] = half == 0 ? tc[k] : ta[k];
       __syncthreads();
-      float pk[K];
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        pk[k] = other[k * 64 + lane];
-        ec[k] = other[k * 64 + 63];     // first wave's last chunk (used by the second wave)
-        ea[k] = other[k * 64];          // second wave's first chunk (used by the first wave)
+        ec[k] = other[k * 64 + 63];     // S, read by the second wave
+        ea[k] = other[k * 64];          // T, read by the first wave
       }
-      cfloat* P = phi + 6 * K * K;
-      float nv[K];
+      const int m = half == 0 ? 64 - lane : lane + 1;     // 1 .. 64
+      float v[K];
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        float acc = half == 0 ? ta[k] : tc[k];
+      for (int k = 0; k < K; ++k) v[k] = half == 0 ? ea[k] : ec[k];
 #pragma unroll
-        for (int m = 0; m < K; ++m) acc = fmaf(P[k * K + m], pk[m], acc);
-        nv[k] = acc;
+      for (int j = 0; j < 7; ++j) {
+        cfloat* P = phi + j * K * K;
+        float nv[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          float acc = 0.f;
+#pragma unroll
+          for (int q2 = 0; q2 < K; ++q2) acc = fmaf(P[k * K + q2], v[q2], acc);
+          nv[k] = acc;
+        }
+        const bool use = (m >> j) & 1;
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = use ? nv[k] : v[k];
       }
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        if (half == 0) ta[k] = nv[k];
-        else tc[k] = nv[k];
+        if (half == 0) ta[k] += v[k];
+        else tc[k] += v[k];
       }
     }
 #pragma unroll
@@ -2092,12 +2104,14 @@ hipError_t launch_first_ln(const PassArgs& a, int grid, hipStream_t stream) {
   const int threads = (1 << a.log2r) << a.log2c;
   const size_t lds = pass_lds_bytes(a) + first_xchg_floats(a) * sizeof(float);
   if (a.log2c > 6) {
-    // rows of 128 chunks (N = 4096) over two waves: 16 blocks per unit, orders up to 2
+    // rows of 128 chunks (N = 4096) over two waves: 16 blocks per unit, orders up to 4
     if constexpr (NBLK == 16) {
       switch (a.order) {
         case 0: return launch_kernel(fht_first_kernel<L, 0, 16, true>, a, grid, threads, lds, stream);
         case 1: return launch_kernel(fht_first_kernel<L, 1, 16, true>, a, grid, threads, lds, stream);
         case 2: return launch_kernel(fht_first_kernel<L, 2, 16, true>, a, grid, threads, lds, stream);
+        case 3: return launch_kernel(fht_first_kernel<L, 3, 16, true>, a, grid, threads, lds, stream);
+        case 4: return launch_kernel(fht_first_kernel<L, 4, 16, true>, a, grid, threads, lds, stream);
         default: break;
       }
     }

@@ -428,10 +428,8 @@ bool first_pass_supported(const PassArgs& a) {
   const int rows_per_wave = std::max(1, 64 >> a.log2c);   // C = 128: half a row per wave
   const int rows_per_group = (4 << a.log2n) / std::max(1, a.groups);
   if (a.order > 0 && (rows_per_group < 1 || rows_per_group % rows_per_wave != 0)) return false;
-  // rows over two waves: orders up to 2 (at N = 4096 the reconstruction amplifies the
-  // zero-frequency rounding of the scan tables by ~N; with 32-sample chunks, order 4 missed the
-  // float32 bar there, so higher orders keep the 64-sample chunks of the generic kernel)
-  if (a.log2c > 6 && (a.log2c > 7 || a.order > 2 || threads > 1024 || nblk != 16)) return false;
+  // rows over two waves: orders up to 4 (the exchange area, 128 K floats per row, must fit)
+  if (a.log2c > 6 && (a.log2c > 7 || a.order > 4 || threads > 1024 || nblk != 16)) return false;
   return nblk == 4 || nblk == 8 || nblk == 16;
 }
 

@@ -168,23 +168,28 @@ def test_reconstruct_matches_oracle(gpu_lib, N, B, order):
 
 def test_reconstruct_4096_rows_over_two_waves(gpu_lib):
     """N = 4096: a row has 128 chunks of 32 samples, so pass 0 spreads each row over two waves
-    and carries the chunk scan's last level between them through LDS (orders up to 2; the
-    filter alone keeps 64-sample chunks).  Against the FP64 oracle, both fused and as the
-    filter followed by the back projection, which takes the other chunking."""
+    and joins their chunk scans through LDS (the filter alone keeps 64-sample chunks).  Orders
+    1 and 2 against the FP64 oracle, fused and as the filter followed by the back projection.
+    Orders 3 and 4: fused against filter-then-back-projection, two float32 chunkings that must
+    agree; against FP64 both sit near or above 1e-5 at this size (the image amplifies the
+    filter's zero-frequency rounding by about N, and these coefficient sets are ill-conditioned
+    there), so the oracle bar is not the check for them."""
     api = gpu_lib
     N = 4096
     ells = I.random_ellipses(N, 10, 4096, disc=0.34, batch=1)
     P = I.linogram(ells, N, device="cuda", dtype=torch.float32)
     Pd = P.cpu().to(torch.float64)
-    for order in (1, 2):
+    for order in (1, 2, 3, 4):
         b, a = _coef(order)
         with api.fbp_plan(N, 1, b, a) as plan:
             got = api.fbp_reconstruct(plan, P).clone()
             two_step = api.fht_backproject(plan, api.fbp_filter(plan, P))
             torch.cuda.synchronize()
-        ref = O.fbp_fht(Pd, torch.tensor(b), torch.tensor(a))
-        assert _rel_rmse(got, ref) < RTOL_RMSE, order
-        assert _rel_rmse(two_step, ref) < RTOL_RMSE, order
+        assert _rel_rmse(got, two_step.cpu().to(torch.float64)) < 1e-6, order
+        if order <= 2:
+            ref = O.fbp_fht(Pd, torch.tensor(b), torch.tensor(a))
+            assert _rel_rmse(got, ref) < RTOL_RMSE, order
+            assert _rel_rmse(two_step, ref) < RTOL_RMSE, order
 
 
 @pytest.mark.parametrize("N,flags", [(512, 4), (1024, 4), (1024, 1), (1024, 2)])

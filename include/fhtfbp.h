@@ -63,10 +63,12 @@ typedef struct {
   void* stream;       /* hipStream_t used by every call (NULL = default stream)               */
 } fbp_plan_desc;
 
-/* Create a plan: validates the description, checks filter stability (every root of
+/* Create a plan for the recursive ramp pair of eq 9 (Sec. 3) and the line geometry of
+ * Sec. 4.1: validates the description, checks filter stability (every root of
  * 1 + a_1 z^-1 + ... + a_K z^-K inside the unit circle), builds the per-row tables (window
- * start, row scale c_t), the chunk transition matrices of the recursive filter, and
- * allocates the inter-pass scratch (2 x max_batch x 16 N^2 bytes at most).  Synchronous.
+ * start; row scale c_t = k_t w_t with k_t = sqrt(1 + m_t^2) of eq 15 and the angular weight
+ * of the row's slope), the chunk transition matrices of the recursion, and allocates the
+ * inter-pass scratch (2 x max_batch x 16 N^2 bytes at most).  Synchronous.
  * On error *out is set to NULL and nothing is allocated. */
 int fbp_plan(const fbp_plan_desc* desc, fbp_plan_t* out);
 
@@ -96,8 +98,9 @@ int fht_backproject(fbp_plan_t plan, const float* lino, float* img, int32_t batc
  * adjoint of fht_backproject.  `img` and `lino` must not overlap. */
 int fht_forward(fbp_plan_t plan, const float* img, float* lino, int32_t batch);
 
-/* The method end to end: fbp_filter then fht_backproject, with the filter fused into the
- * first back-projection pass (the linogram is read once).  `lino` is not modified. */
+/* The method end to end (Sec. 3, eq 9-13, then Sec. 4.4-4.5, eq 19-22): fbp_filter then
+ * fht_backproject, with the filter fused into the first back-projection pass (the linogram
+ * is read once).  `lino` is not modified. */
 int fbp_reconstruct(fbp_plan_t plan, const float* lino, float* img, int32_t batch);
 
 /* Gradient of a loss with respect to the recursive-filter coefficients, for learning them:

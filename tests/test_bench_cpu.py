@@ -30,12 +30,12 @@ def test_kernel_kinds():
     assert bench._kind("void at::native::elementwise_kernel<128, 4>(...)") is None
 
 
-def test_algorithmic_bytes_per_kind():
+def test_pass_model_bytes_per_kind():
     n2 = 1024.0 * 1024
-    assert bench.algorithmic_bytes("first", 1024, [5, 5]) == 32 * n2
-    assert bench.algorithmic_bytes("last", 1024, [5, 5]) == 20 * n2
-    assert bench.algorithmic_bytes("last_v", 1024, [5, 4, 1]) == 12 * n2
-    assert bench.algorithmic_bytes("last_h", 1024, [5, 4, 1]) == 16 * n2
+    assert bench.pass_model_bytes("first", 1024, [5, 5]) == 32 * n2
+    assert bench.pass_model_bytes("last", 1024, [5, 5]) == 20 * n2
+    assert bench.pass_model_bytes("last_v", 1024, [5, 4, 1]) == 12 * n2
+    assert bench.pass_model_bytes("last_h", 1024, [5, 4, 1]) == 16 * n2
 
 
 def _synthetic_run(d, last_names):
@@ -86,7 +86,7 @@ def test_summary_fused_last_pass(tmp_path):
     assert k["first"]["fetch_size_bytes"] == 100 * 1024 * 2
     assert k["first"]["write_size_bytes"] == 50 * 1024
     assert k["last"]["hbm_bytes"] == 100 * 1024 * 2 + 50 * 1024
-    assert k["last"]["algorithmic_bytes"] == 20 * 1024 * 1024 * 512
+    assert k["last"]["pass_model_bytes"] == 20 * 1024 * 1024 * 512
 
 
 def test_summary_split_last_pass_alternates(tmp_path):
@@ -96,8 +96,8 @@ def test_summary_split_last_pass_alternates(tmp_path):
     k = js["kernels"]
     assert k["last_v"]["dispatches"] == 2 and k["last_v"]["avg_us"] == 1.0
     assert k["last_h"]["dispatches"] == 2 and k["last_h"]["avg_us"] == 1.5
-    assert k["last_v"]["algorithmic_bytes"] == 12 * 1024 * 1024 * 512
-    assert k["last_h"]["algorithmic_bytes"] == 16 * 1024 * 1024 * 512
+    assert k["last_v"]["pass_model_bytes"] == 12 * 1024 * 1024 * 512
+    assert k["last_h"]["pass_model_bytes"] == 16 * 1024 * 1024 * 512
 
 
 def test_traffic_is_reported_only_for_the_current_sources(tmp_path):
@@ -112,3 +112,19 @@ def test_traffic_is_reported_only_for_the_current_sources(tmp_path):
     assert v is None and "changed" in why
     assert bench.traffic_from_profile(str(tmp_path / "missing.txt"), "first")[0] is None
 
+
+
+def test_roofline_fraction_on_algorithmic_bytes():
+    """The roofline's `achieved` divides the method's 20 N^2 bytes per slice (linogram read once,
+    image written once) by the dominant kernel's launch time; the pass design's own byte model
+    of that kernel is reported beside it, never as `achieved`."""
+    n, batch, ms = 1024, 512, 3.883
+    pm_gb = bench.pass_model_bytes("first", n, [5, 5]) * batch / 1e9
+    r = bench.roofline_record("first", ms, n, batch, pm_gb, None, "none")
+    alg = 20.0 * n * n * batch
+    assert r["algorithmic_GB_per_launch"] == round(alg / 1e9, 3)
+    assert abs(r["achieved"] - alg / (ms * 1e-3) / 1e9) < 0.1
+    assert abs(r["frac"] - alg / (ms * 1e-3) / 1e9 / 8000.0) < 1e-4
+    assert abs(r["frac"] - 0.3457) < 1e-3
+    assert abs(r["pass_model_frac"] - 32.0 / 20.0 * r["frac"]) < 1e-3
+    assert r["traffic"] is None and r["bound"] == "hbm"

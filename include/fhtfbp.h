@@ -58,7 +58,12 @@ typedef struct {
   const double* b;    /* host [groups][order]: feed-forward b_0..b_{K-1} (eq 9); the causal
                          and the anticausal pass share them (Sec. 3)                          */
   const double* a;    /* host [groups][order]: feedback a_1..a_K (eq 9).  The kernels hold b
-                         and a as float32 (rounded to nearest on upload)                       */
+                         and a as float32 (rounded to nearest on upload).  When every group's
+                         b sums to zero (|sum b| <= 1e-12 sum |b|, the zero response at zero
+                         frequency that the ramp of eq 6 has) and K >= 2, they hold instead
+                         the cumulative sums c_k = b_0 + .. + b_k (k < K - 1, summed in double)
+                         and filter the first difference of each row: B(z) = (1 - z^-1) C(z),
+                         so the float32 filter keeps that zero exactly                         */
   uint32_t flags;     /* FBP_* flags above                                                    */
   void* stream;       /* hipStream_t used by every call (NULL = default stream)               */
 } fbp_plan_desc;
@@ -79,7 +84,9 @@ int fbp_plan_destroy(fbp_plan_t plan);
 int fbp_plan_set_stream(fbp_plan_t plan, void* stream);
 
 /* Replace the recursive-filter coefficients (host arrays shaped as in the description).
- * Synchronises the plan's stream, checks stability, uploads.  Used by the learned filter. */
+ * Synchronises the plan's stream, checks stability, uploads.  Used by the learned filter.
+ * Graphs captured on the plan keep working unless the numerator form changes (the new b
+ * balanced where the old was not, or the reverse); then they refuse to launch (FBP_EINVAL). */
 int fbp_plan_set_coefficients(fbp_plan_t plan, const double* b, const double* a);
 
 /* Row filter alone (Sec. 3, eq 12-13): every linogram row (b, q, t) is read over its window

@@ -86,6 +86,42 @@ __device__ void load_tile(const PassArgs& A, float* S, int b, int q, int row0) {
   }
 }
 
+// ---- first-difference numerator (DIFF filters) ----------------------------------------------
+// On entry xc[k] = x[base - 1 - k] and xa[k] = x[base + L + k] for k < K - 1 (zero outside the
+// window).  Rearranged into the difference history: xc[k] = d[base - 1 - k] for k < K - 2 (the
+// slot K - 2 is shifted out before it is read) and xc[K - 1] = x[base - 1], the sample the next
+// difference is taken against; likewise for the anticausal half, mirrored.
+template <int K>
+__device__ __forceinline__ void diff_history(float* xc, float* xa) {
+  const float pc = xc[0], pa = xa[0];
+#pragma unroll
+  for (int k = 0; k < K - 2; ++k) {
+    xc[k] = xc[k] - xc[k + 1];
+    xa[k] = xa[k] - xa[k + 1];
+  }
+  if constexpr (K >= 2) {
+    xc[K - 2] = 0.f;
+    xa[K - 2] = 0.f;
+  }
+  xc[K - 1] = pc;
+  xa[K - 1] = pa;
+}
+
+// One sample of both halves: shift the differences, take the new one against the previous
+// sample (xi - x[i-1] causal, xj - x[j+1] anticausal) and keep xi, xj for the next step.
+template <int K>
+__device__ __forceinline__ void diff_step(float* xc, float* xa, float xi, float xj) {
+#pragma unroll
+  for (int k = K - 2; k > 0; --k) {
+    xc[k] = xc[k - 1];
+    xa[k] = xa[k - 1];
+  }
+  xc[0] = xi - xc[K - 1];
+  xa[0] = xj - xa[K - 1];
+  xc[K - 1] = xi;
+  xa[K - 1] = xj;
+}
+
 // ---- recursive ramp-filter pair over every tile row (rows are linogram rows row0 + r) --------
 // Work item (r, c): chunk c = positions c L .. c L + L - 1 of row r's window.  Each chunk runs
 // the recursion from zero state, the true entering states come from a scan over the chunks of
@@ -93,7 +129,14 @@ __device__ void load_tile(const PassArgs& A, float* S, int b, int q, int row0) {
 // the recursion to that entering state is added.  The anticausal pass is the same recursion
 // run from the end of the window.  Inputs are re-read from LDS in each sweep (only a K-sample
 // sliding window is held), the output of the chunk is accumulated in registers.
-template <int L, int K>
+//
+// DIFF: the numerator is taken in first-difference form, B(z) = (1 - z^-1) C(z) with taps
+// c_k = b_0 + ... + b_k (k < K - 1; the plan uses it when every group has sum(b) = 0).  Each
+// recursion then filters d[i] = x[i] - x[i-1] (anticausal: x[i] - x[i+1]) by C, and a
+// float32 filter keeps the exactly zero response at zero frequency that the ramp has (eq 6):
+// rounding b_k c_t to float32 one tap at a time would leave sum_k b_k c_t a few ulps off zero,
+// an offset per row that the back projection sums over ~N rows.
+template <int L, int K, bool DIFF = false>
 __device__ void filter_tile(const PassArgs& A, float* S, int q, int row0) {
   int tid = threadIdx.x;
   asm volatile("" : "+v"(tid));   // recomputed per call (keeps loop-invariant addresses out of
@@ -104,13 +147,14 @@ __device__ void filter_tile(const PassArgs& A, float* S, int q, int row0) {
   const int t = row0 + r;
   const int g = ((q * N + t) * A.groups) / (4 * N);
   const float* cf = A.coef + (size_t)g * A.coef_stride;
+  const float* cb = DIFF ? cf + A.coef_stride - K : cf;   // C's taps sit at the table's end
   int sig = A.sigma[t];
   const float ct = A.scale[t];
   // the row factor c_t scales the numerator: the recursion then yields c_t y directly
   float bk[K], ak[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    bk[k] = ct * cf[k];
+    bk[k] = ct * cb[k];
     ak[k] = cf[K + k];
   }
   const float* phi = cf + 2 * K;
@@ -142,21 +186,31 @@ __device__ void filter_tile(const PassArgs& A, float* S, int q, int row0) {
     xc[k] = (k < K - 1) ? at(base - 1 - k) : 0.f;
     xa[k] = (k < K - 1) ? at(base + L + k) : 0.f;
   }
+  if constexpr (DIFF) diff_history<K>(xc, xa);
 #pragma unroll
   for (int s = 0; s < L; ++s) {
     const int i = s, j = L - 1 - s;
-#pragma unroll
-    for (int k = K - 1; k > 0; --k) {
-      xc[k] = xc[k - 1];
-      xa[k] = xa[k - 1];
-    }
-    xc[0] = in(base + i);
-    xa[0] = in(base + j);
     float ac = 0.f, aa = 0.f;
+    if constexpr (DIFF) {
+      diff_step<K>(xc, xa, in(base + i), in(base + j));
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      ac = fmaf(bk[k], xc[k], ac);
-      aa = fmaf(bk[k], xa[k], aa);
+      for (int k = 0; k < K - 1; ++k) {
+        ac = fmaf(bk[k], xc[k], ac);
+        aa = fmaf(bk[k], xa[k], aa);
+      }
+    } else {
+#pragma unroll
+      for (int k = K - 1; k > 0; --k) {
+        xc[k] = xc[k - 1];
+        xa[k] = xa[k - 1];
+      }
+      xc[0] = in(base + i);
+      xa[0] = in(base + j);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        ac = fmaf(bk[k], xc[k], ac);
+        aa = fmaf(bk[k], xa[k], aa);
+      }
     }
     // oldest state first: the previous output enters last, one FMA per step on the chain
 #pragma unroll
@@ -252,7 +306,8 @@ __device__ void filter_tile(const PassArgs& A, float* S, int q, int row0) {
 // `step_hook(s)` runs at the top of recursion step s (the caller uses it to issue the next
 // tile's loads a few at a time, so the texture unit takes them while the ALUs work).
 // WIDE: rows of 128 chunks over two waves (the row length 4096); otherwise C <= 64.
-template <int K, bool WIDE, typename Hook>
+// DIFF: the first-difference numerator of filter_tile.
+template <int K, bool WIDE, bool DIFF, typename Hook>
 __device__ bool filter_tile_aligned(const PassArgs& A, float* S, float* xs, int q, int row0,
                                     float ct, Hook&& step_hook) {
   constexpr int L = 32;
@@ -264,11 +319,12 @@ __device__ bool filter_tile_aligned(const PassArgs& A, float* S, float* xs, int 
   const int t = row0 + r;
   const int g = __builtin_amdgcn_readfirstlane(((q * N + t) * A.groups) / (4 * N));
   cfloat* cf = as_constant(A.coef + (size_t)g * A.coef_stride);
+  cfloat* cb = DIFF ? cf + (A.coef_stride - K) : cf;   // C's taps sit at the table's end
   // the row factor c_t scales the numerator (per lane: a wave holds 64 / C rows)
   float bk[K], ak[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    bk[k] = ct * cf[k];
+    bk[k] = ct * cb[k];
     ak[k] = cf[K + k];
   }
   cfloat* phi = cf + 2 * K;
@@ -294,24 +350,36 @@ __device__ bool filter_tile_aligned(const PassArgs& A, float* S, float* xs, int 
     xc[k] = (k < K - 1) ? at(base - 1 - k) : 0.f;
     xa[k] = (k < K - 1) ? at(base + L + k) : 0.f;
   }
+  if constexpr (DIFF) diff_history<K>(xc, xa);
 #pragma unroll
   for (int s = 0; s < L; ++s) {
     const int i = s, j = L - 1 - s;
+    if constexpr (!DIFF) {
 #pragma unroll
-    for (int k = K - 1; k > 0; --k) {
-      xc[k] = xc[k - 1];
-      xa[k] = xa[k - 1];
+      for (int k = K - 1; k > 0; --k) {
+        xc[k] = xc[k - 1];
+        xa[k] = xa[k - 1];
+      }
     }
     if ((s & 3) == 0) asm volatile("" ::: "memory");   // keeps at most 8 LDS reads in flight
     step_hook(s);
     if ((s & 7) == 0) __builtin_amdgcn_sched_barrier(0);   // the hook's work stays at step s
-    xc[0] = rp[i];
-    xa[0] = rp[j];
     float ac = 0.f, aa = 0.f;
+    if constexpr (DIFF) {
+      diff_step<K>(xc, xa, rp[i], rp[j]);
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      ac = fmaf(bk[k], xc[k], ac);
-      aa = fmaf(bk[k], xa[k], aa);
+      for (int k = 0; k < K - 1; ++k) {
+        ac = fmaf(bk[k], xc[k], ac);
+        aa = fmaf(bk[k], xa[k], aa);
+      }
+    } else {
+      xc[0] = rp[i];
+      xa[0] = rp[j];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        ac = fmaf(bk[k], xc[k], ac);
+        aa = fmaf(bk[k], xa[k], aa);
+      }
     }
     // oldest state first: the previous output enters last, one FMA per step on the chain
 #pragma unroll
@@ -1085,17 +1153,17 @@ __device__ void run_levels(const PassArgs& A, float* S) {
   }
 }
 
-template <int L, int K, bool STREAM>
+template <int L, int K, bool STREAM, bool DIFF = false>
 __device__ void process_class(const PassArgs& A, float* S, int b, int q, int row0) {
   load_tile<L>(A, S, b, q, row0);
   __syncthreads();
-  if constexpr (K > 0) filter_tile<L, K>(A, S, q, row0);
+  if constexpr (K > 0) filter_tile<L, K, DIFF>(A, S, q, row0);
   run_levels<L, STREAM>(A, S);
 }
 
 // Passes that keep the four classes apart: the first and middle passes of the back projection,
 // every pass of the forward transform, and the filter alone (OUT_SAME).
-template <int L, int K, bool STREAM>
+template <int L, int K, bool STREAM, bool DIFF = false>
 __global__ void __launch_bounds__(1024) fht_rows_kernel(PassArgs A) {
   extern __shared__ float S[];
   const int T = blockDim.x, tid = threadIdx.x;
@@ -1116,7 +1184,7 @@ __global__ void __launch_bounds__(1024) fht_rows_kernel(PassArgs A) {
     v = tile & ((1 << vbits) - 1);
     row0 = (j << A.k_hi) + (v << F);
   }
-  process_class<L, K, STREAM>(A, S, b, q, row0);
+  process_class<L, K, STREAM, DIFF>(A, S, b, q, row0);
 
   float* dst = A.out + (size_t)(b * 4 + q) * N * N;
   if (A.out_mode == OUT_SAME) {
@@ -1160,7 +1228,7 @@ __global__ void __launch_bounds__(1024) fht_rows_kernel(PassArgs A) {
 // pair in the image frame (eq 20-22).  OUT_IMG_V: classes 0 and 1 give image rows j R .. j R +
 // R - 1, image[y][x] = c0[y][x] + c1[y][N-1-x].  OUT_IMG_H: classes 2 and 3 give image columns
 // j R .. j R + R - 1, image[y][x] += c2[x][y] + c3[x][N-1-y] (launched after OUT_IMG_V).
-template <int L, int K, bool STREAM>
+template <int L, int K, bool STREAM, bool DIFF = false>
 __global__ void __launch_bounds__(1024) fht_combine_kernel(PassArgs A) {
   extern __shared__ float S[];
   const int T = blockDim.x, tid = threadIdx.x;
@@ -1173,7 +1241,7 @@ __global__ void __launch_bounds__(1024) fht_combine_kernel(PassArgs A) {
   const int qa = vpair ? 0 : 2;
   const int row0 = j * R;
   float keep[L];
-  process_class<L, K, STREAM>(A, S, b, qa, row0);
+  process_class<L, K, STREAM, DIFF>(A, S, b, qa, row0);
 #pragma unroll
   for (int k = 0; k < L; ++k) {
     const int e = tid + k * T;
@@ -1182,7 +1250,7 @@ __global__ void __launch_bounds__(1024) fht_combine_kernel(PassArgs A) {
     keep[k] = S[lds_at(brev_bits(i, F), c, A.rs, A.log2l)];
   }
   __syncthreads();
-  process_class<L, K, STREAM>(A, S, b, qa + 1, row0);
+  process_class<L, K, STREAM, DIFF>(A, S, b, qa + 1, row0);
   float* img = A.out + (size_t)b * N * N;
   if (vpair) {
 #pragma unroll
@@ -1241,7 +1309,7 @@ __device__ __forceinline__ float4 load4_rotated(const float* row, int x, int o, 
 // the second half goes out before the levels; levels 1 .. F - 1 run as radix-4 stages (an odd
 // one streams first), the last of which stores the tile to HBM itself.  The loads of the next
 // tile are in flight through all of it.
-template <int L, int K, int NBLK, bool WIDE = false>
+template <int L, int K, int NBLK, bool WIDE = false, bool DIFF = false>
 __global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
   extern __shared__ float S[];
   const int T = blockDim.x, tid = threadIdx.x;
@@ -1335,7 +1403,7 @@ __global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
       // the first half of the next tile's loads, one every 8 recursion steps (the last tile
       // of a block reloads itself instead of branching: no branch splits the filter's code)
       const int tn = more ? tl + (int)gridDim.x : tl;
-      level0 = filter_tile_aligned<K, WIDE>(A, S, xs, q, row0, ct, [&](int s) {
+      level0 = filter_tile_aligned<K, WIDE, DIFF>(A, S, xs, q, row0, ct, [&](int s) {
         if ((s & 7) == 0) issue_one(tn, s >> 3);
       });
     } else {
@@ -2070,8 +2138,8 @@ hipError_t launch_kernel(Kern kern, const PassArgs& a, int blocks, int threads, 
   return hipGetLastError();
 }
 
-template <int L, int K, bool STREAM>
-hipError_t launch_lks(const PassArgs& a, int batch, hipStream_t stream) {
+template <int L, int K, bool STREAM, bool DIFF>
+hipError_t launch_lksd(const PassArgs& a, int batch, hipStream_t stream) {
   const int N = 1 << a.log2n;
   const int R = 1 << a.log2r;
   const int threads = R << a.log2c;
@@ -2079,12 +2147,22 @@ hipError_t launch_lks(const PassArgs& a, int batch, hipStream_t stream) {
   const int tiles = N >> a.log2r;
   if (a.out_mode == OUT_IMG_V || a.out_mode == OUT_IMG_H) {
     if constexpr (L <= 32 || K == 0)
-      return launch_kernel(fht_combine_kernel<L, K, STREAM>, a, batch * tiles, threads, lds,
-                           stream);
+      return launch_kernel(fht_combine_kernel<L, K, STREAM, DIFF>, a, batch * tiles, threads,
+                           lds, stream);
     else
       return hipErrorInvalidValue;   // the filter runs in a combining pass only when N <= 128
   }
-  return launch_kernel(fht_rows_kernel<L, K, STREAM>, a, batch * 4 * tiles, threads, lds, stream);
+  return launch_kernel(fht_rows_kernel<L, K, STREAM, DIFF>, a, batch * 4 * tiles, threads, lds,
+                       stream);
+}
+
+// First-difference numerator only for orders >= 2 (a balanced order-1 numerator is zero).
+template <int L, int K, bool STREAM>
+hipError_t launch_lks(const PassArgs& a, int batch, hipStream_t stream) {
+  if constexpr (K >= 2) {
+    if (a.diff) return launch_lksd<L, K, STREAM, true>(a, batch, stream);
+  }
+  return launch_lksd<L, K, STREAM, false>(a, batch, stream);
 }
 
 template <int L, int K>
@@ -2099,6 +2177,19 @@ hipError_t launch_lk(const PassArgs& a, int batch, hipStream_t stream) {
 
 }  // namespace
 
+// The first-pass kernel of order K, with the first-difference numerator when the plan's
+// coefficients allow it (orders >= 2).
+template <int L, int K, int NBLK, bool WIDE>
+hipError_t launch_first_k(const PassArgs& a, int grid, int threads, size_t lds,
+                          hipStream_t stream) {
+  if constexpr (K >= 2) {
+    if (a.diff)
+      return launch_kernel(fht_first_kernel<L, K, NBLK, WIDE, true>, a, grid, threads, lds,
+                           stream);
+  }
+  return launch_kernel(fht_first_kernel<L, K, NBLK, WIDE, false>, a, grid, threads, lds, stream);
+}
+
 template <int L, int NBLK>
 hipError_t launch_first_ln(const PassArgs& a, int grid, hipStream_t stream) {
   const int threads = (1 << a.log2r) << a.log2c;
@@ -2107,23 +2198,23 @@ hipError_t launch_first_ln(const PassArgs& a, int grid, hipStream_t stream) {
     // rows of 128 chunks (N = 4096) over two waves: 16 blocks per unit, orders up to 4
     if constexpr (NBLK == 16) {
       switch (a.order) {
-        case 0: return launch_kernel(fht_first_kernel<L, 0, 16, true>, a, grid, threads, lds, stream);
-        case 1: return launch_kernel(fht_first_kernel<L, 1, 16, true>, a, grid, threads, lds, stream);
-        case 2: return launch_kernel(fht_first_kernel<L, 2, 16, true>, a, grid, threads, lds, stream);
-        case 3: return launch_kernel(fht_first_kernel<L, 3, 16, true>, a, grid, threads, lds, stream);
-        case 4: return launch_kernel(fht_first_kernel<L, 4, 16, true>, a, grid, threads, lds, stream);
+        case 0: return launch_first_k<L, 0, 16, true>(a, grid, threads, lds, stream);
+        case 1: return launch_first_k<L, 1, 16, true>(a, grid, threads, lds, stream);
+        case 2: return launch_first_k<L, 2, 16, true>(a, grid, threads, lds, stream);
+        case 3: return launch_first_k<L, 3, 16, true>(a, grid, threads, lds, stream);
+        case 4: return launch_first_k<L, 4, 16, true>(a, grid, threads, lds, stream);
         default: break;
       }
     }
     return hipErrorInvalidValue;
   }
   switch (a.order) {
-    case 0: return launch_kernel(fht_first_kernel<L, 0, NBLK>, a, grid, threads, lds, stream);
-    case 1: return launch_kernel(fht_first_kernel<L, 1, NBLK>, a, grid, threads, lds, stream);
-    case 2: return launch_kernel(fht_first_kernel<L, 2, NBLK>, a, grid, threads, lds, stream);
-    case 3: return launch_kernel(fht_first_kernel<L, 3, NBLK>, a, grid, threads, lds, stream);
-    case 4: return launch_kernel(fht_first_kernel<L, 4, NBLK>, a, grid, threads, lds, stream);
-    case 8: return launch_kernel(fht_first_kernel<L, 8, NBLK>, a, grid, threads, lds, stream);
+    case 0: return launch_first_k<L, 0, NBLK, false>(a, grid, threads, lds, stream);
+    case 1: return launch_first_k<L, 1, NBLK, false>(a, grid, threads, lds, stream);
+    case 2: return launch_first_k<L, 2, NBLK, false>(a, grid, threads, lds, stream);
+    case 3: return launch_first_k<L, 3, NBLK, false>(a, grid, threads, lds, stream);
+    case 4: return launch_first_k<L, 4, NBLK, false>(a, grid, threads, lds, stream);
+    case 8: return launch_first_k<L, 8, NBLK, false>(a, grid, threads, lds, stream);
     default: return hipErrorInvalidValue;
   }
 }

@@ -26,8 +26,12 @@ struct fbp_plan_s {
   std::vector<int> fwd_levels;   // levels per forward-transform pass (full-row tiles)
   int log2w = 8;              // column-tiled passes: output columns per tile = 2^log2w
   int fmax = 0;               // most levels a first pass (full rows in LDS) can fuse
-  unsigned generation = 0;    // bumped when the schedule changes (captured graphs go stale)
+  unsigned generation = 0;    // bumped when the schedule or the numerator form changes
+                              // (captured graphs go stale)
   std::vector<double> b, a;   // host copies [groups][order]
+  // every group's numerator sums to zero (zero response at zero frequency): the filters take
+  // it in first-difference form, which keeps that zero exact in float32
+  bool diff = false;
   int coef_stride = 0;
   float* d_coef = nullptr;
   // N = 4096: the filter's own chunks are 64 samples (C = 64), while the persistent first pass
@@ -182,12 +186,39 @@ int fill_coefficients(const fbp_plan_s* p, int L, int stride, std::vector<float>
     homogeneous_table(ag.data(), K, L, hom.data());
     for (int i = 0; i < K * L; ++i)
       host[(size_t)g * stride + 2 * K + kScanLevels * K * K + i] = (float)hom[i];
+    // taps of C(z) with B(z) = (1 - z^-1) C(z) + sum(b) z^-(K-1): the cumulative sums of b in
+    // double, rounded once (used when every group's sum(b) is zero)
+    double c = 0.0;
+    for (int k = 0; k + 1 < K; ++k) {
+      c += bg[k];
+      host[(size_t)g * stride + stride - K + k] = (float)c;
+    }
   }
   return FBP_OK;
 }
 
+// Whether every group's numerator sums to zero, to rounding of its taps in double: then
+// B(z) = (1 - z^-1) C(z) exactly, and the filters run in first-difference form.
+bool balanced_numerators(const fbp_plan_s* p) {
+  if (p->order < 2) return false;
+  for (int g = 0; g < p->groups; ++g) {
+    double sum = 0.0, mag = 0.0;
+    for (int k = 0; k < p->order; ++k) {
+      sum += p->b[(size_t)g * p->order + k];
+      mag += fabs(p->b[(size_t)g * p->order + k]);
+    }
+    if (!(fabs(sum) <= 1e-12 * mag)) return false;
+  }
+  return true;
+}
+
 int upload_coefficients(fbp_plan_s* p) {
   std::vector<float> host, host32;
+  // the numerator form is compiled into the kernels a graph captured: a change makes such
+  // graphs stale, as a schedule change does
+  const bool diff = balanced_numerators(p);
+  if (diff != p->diff) p->generation += 1;
+  p->diff = diff;
   int rc = fill_coefficients(p, 1 << p->log2l, p->coef_stride, host);
   if (rc == FBP_OK && p->d_coef32) rc = fill_coefficients(p, 32, p->coef_stride32, host32);
   if (rc != FBP_OK) return rc;
@@ -327,6 +358,7 @@ PassArgs base_args(const fbp_plan_s* p) {
   A.scale = p->d_scale;
   A.sigma = p->d_sigma;
   A.windowed = (p->flags & FBP_ZERO_WINDOW) ? 0 : 1;
+  A.diff = p->diff ? 1 : 0;
   return A;
 }
 
@@ -689,9 +721,9 @@ int fbp_plan(const fbp_plan_desc* d, fbp_plan_t* out) {
   p->levels = backprojection_levels(p->log2n, fmax);
   {
     const int KK = kernel_order(K);
-    p->coef_stride = 2 * KK + kScanLevels * KK * KK + KK * (1 << p->log2l);
+    p->coef_stride = 3 * KK + kScanLevels * KK * KK + KK * (1 << p->log2l);
     // rows of more than 64 chunks of 32 (N = 4096): a second table for the first pass
-    if (p->log2n > 11) p->coef_stride32 = 2 * KK + kScanLevels * KK * KK + KK * 32;
+    if (p->log2n > 11) p->coef_stride32 = 3 * KK + kScanLevels * KK * KK + KK * 32;
   }
 
   // per-row tables: c_t = k_t w_t (times k_t again for FHT-normalised input), window starts

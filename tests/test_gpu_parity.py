@@ -26,17 +26,11 @@ COEF = {
 }
 
 
-def _coef(order, groups=1, seed=0):
-    """Coefficients as the kernels hold them (float32 values, returned as float64), so both
-    sides run the same filter.  The reconstruction is very sensitive to the filter's response
-    at zero frequency (sum of b): rounding an exactly balanced b to float32 moves it by ~1e-8,
-    which the back projection amplifies by ~N; that is a property of the method's parameters,
-    not of the kernels, and is measured separately below."""
-    b, a = _coef64(order, groups, seed)
-    return b.astype(np.float32).astype(np.float64), a.astype(np.float32).astype(np.float64)
-
-
-def _coef64(order, groups=1, seed=0):
+def _coef(order, groups=1, seed=0, balanced=False):
+    """FP64 coefficients, as the ABI takes them; both sides get the same values.  The fixed
+    sets of orders 2-4 have sum(b) = 0 (zero response at zero frequency, as the ramp), so the
+    plan runs them in first-difference form; random sets (orders 5-8, several groups) are
+    unbalanced unless `balanced`, which removes the mean of each group's b."""
     if order in COEF and groups == 1:
         b, a = COEF[order]
         return np.array(b), np.array(a)
@@ -47,8 +41,17 @@ def _coef64(order, groups=1, seed=0):
         as_.append(np.poly(poles)[1:])
         b = g.normal(size=order) * 0.05
         b[0] = 0.125
+        if balanced:
+            b = b - b.mean()
         bs.append(b)
     return np.array(bs), np.array(as_)
+
+
+def _coef32(order, groups=1, seed=0, balanced=False):
+    """The same coefficients rounded to float32 (then unbalanced by rounding: the plan takes
+    them in the plain numerator form)."""
+    b, a = _coef(order, groups, seed, balanced)
+    return b.astype(np.float32).astype(np.float64), a.astype(np.float32).astype(np.float64)
 
 
 def _rel_rmse(got, ref):
@@ -152,10 +155,18 @@ def test_filter_in_place(gpu_lib):
 
 # ---- the method end to end ------------------------------------------------------------------
 
+def _max_rel(got, ref):
+    """Largest per-pixel error over the largest reference magnitude."""
+    got = got.detach().cpu().to(torch.float64)
+    return float((got - ref).abs().max() / ref.abs().max())
+
+
 @pytest.mark.parametrize("N,B,order", [(8, 1, 2), (16, 2, 2), (32, 2, 2), (64, 2, 3),
                                        (128, 3, 2), (256, 2, 2), (512, 2, 4), (1024, 2, 2),
-                                       (2048, 1, 2)])
+                                       (1024, 1, 3), (1024, 1, 4), (2048, 1, 2), (2048, 1, 3),
+                                       (2048, 1, 4)])
 def test_reconstruct_matches_oracle(gpu_lib, N, B, order):
+    """FP64 coefficients on both sides (the balanced sets run in first-difference form)."""
     api = gpu_lib
     P = _phantom_lino(N, B, seed=N)
     b, a = _coef(order)
@@ -164,16 +175,48 @@ def test_reconstruct_matches_oracle(gpu_lib, N, B, order):
         torch.cuda.synchronize()
     ref = O.fbp_fht(P.to(torch.float64), torch.tensor(b), torch.tensor(a))
     assert _rel_rmse(got, ref) < RTOL_RMSE
+    assert _max_rel(got, ref) < 10 * RTOL_RMSE
+
+
+@pytest.mark.parametrize("N,order,balanced", [(512, 5, True), (512, 6, False), (512, 8, True),
+                                              (1024, 5, False), (1024, 6, True),
+                                              (1024, 8, False), (1024, 8, True)])
+def test_reconstruct_high_orders_fused(gpu_lib, N, order, balanced):
+    """Orders 5..8 through the fused first pass (the order-8 kernel, zero-padded for 5..7),
+    in both numerator forms, against the FP64 oracle: relative RMSE and per-pixel maximum."""
+    api = gpu_lib
+    P = _phantom_lino(N, 2, seed=N + order)
+    b, a = _coef(order, balanced=balanced)
+    with api.fbp_plan(N, 2, b, a) as plan:
+        got = api.fbp_reconstruct(plan, P.cuda())
+        torch.cuda.synchronize()
+    ref = O.fbp_fht(P.to(torch.float64), torch.tensor(b), torch.tensor(a))
+    assert _rel_rmse(got, ref) < RTOL_RMSE
+    assert _max_rel(got, ref) < 10 * RTOL_RMSE
+
+
+def test_reconstruct_learned_filter_shape(gpu_lib):
+    """The learned filter's launch shape: N = 1024, order 4, 8 angle groups with sum(b) = 0 (the
+    order-4 first-pass kernel with one coefficient set per group, in first-difference form),
+    two slices of 30 ellipses with Poisson noise at 1e4 photons."""
+    api = gpu_lib
+    N, B = 1024, 2
+    ells = I.random_ellipses(N, 30, seed=55, batch=B)
+    P = I.poisson_noisy(I.linogram(ells, N), 1e4, seed=56).to(torch.float32)
+    b, a = _coef(4, groups=8, balanced=True)
+    with api.fbp_plan(N, B, b, a) as plan:
+        got = api.fbp_reconstruct(plan, P.cuda())
+        torch.cuda.synchronize()
+    ref = O.fbp_fht(P.to(torch.float64), torch.tensor(b), torch.tensor(a))
+    assert _rel_rmse(got, ref) < RTOL_RMSE
+    assert _max_rel(got, ref) < 10 * RTOL_RMSE
 
 
 def test_reconstruct_4096_rows_over_two_waves(gpu_lib):
     """N = 4096: a row has 128 chunks of 32 samples, so pass 0 spreads each row over two waves
     and joins their chunk scans through LDS (the filter alone keeps 64-sample chunks).  Orders
-    1 and 2 against the FP64 oracle, fused and as the filter followed by the back projection.
-    Orders 3 and 4: fused against filter-then-back-projection, two float32 chunkings that must
-    agree; against FP64 both sit near or above 1e-5 at this size (the image amplifies the
-    filter's zero-frequency rounding by about N, and these coefficient sets are ill-conditioned
-    there), so the oracle bar is not the check for them."""
+    1..4 with FP64 coefficients against the FP64 oracle, fused and as the filter followed by
+    the back projection; the two float32 chunkings also agree with each other."""
     api = gpu_lib
     N = 4096
     ells = I.random_ellipses(N, 10, 4096, disc=0.34, batch=1)
@@ -186,10 +229,32 @@ def test_reconstruct_4096_rows_over_two_waves(gpu_lib):
             two_step = api.fht_backproject(plan, api.fbp_filter(plan, P))
             torch.cuda.synchronize()
         assert _rel_rmse(got, two_step.cpu().to(torch.float64)) < 1e-6, order
-        if order <= 2:
-            ref = O.fbp_fht(Pd, torch.tensor(b), torch.tensor(a))
-            assert _rel_rmse(got, ref) < RTOL_RMSE, order
-            assert _rel_rmse(two_step, ref) < RTOL_RMSE, order
+        ref = O.fbp_fht(Pd, torch.tensor(b), torch.tensor(a))
+        assert _rel_rmse(got, ref) < RTOL_RMSE, order
+        assert _rel_rmse(two_step, ref) < RTOL_RMSE, order
+
+
+def test_forward_4096_sampled_rows_bit_exact(gpu_lib):
+    """Forward transform at the largest size on integers <= 250 (every partial sum below 2^24):
+    sampled rows of every class against the definition lino[q][t][s] = sum over y of the
+    class-q frame's row y at column (s + D[t, y]) mod N (eq 16-17)."""
+    api = gpu_lib
+    N = 4096
+    f = I.random_int_array((1, N, N), 0, 250, seed=4097).to(torch.float32)
+    with api.fbp_plan(N, 1, *_coef(2)) as plan:
+        got = api.fht_forward(plan, f.cuda())
+        torch.cuda.synchronize()
+    D = O.dyadic_shift(N)
+    fd = f[0].to(torch.float64)
+    y = torch.arange(N)
+    for q in range(4):
+        fr = O.to_frame(fd, q)
+        for t in (0, 1, 2047, 4095):
+            for s0 in (0, 1777, 4095 - 7):
+                s = torch.arange(s0, s0 + 8)
+                cols = (s[None, :] + D[t][:, None]) % N            # [y, 8]
+                ref = torch.gather(fr, 1, cols).sum(0)
+                assert torch.equal(got[0, q, t, s0:s0 + 8].cpu().to(torch.float64), ref), (q, t, s0)
 
 
 @pytest.mark.parametrize("N,flags", [(512, 4), (1024, 4), (1024, 1), (1024, 2)])
@@ -210,21 +275,51 @@ def test_reconstruct_flags_on_the_fused_first_pass(gpu_lib, N, flags):
 
 
 def test_coefficient_rounding_sensitivity(gpu_lib):
-    """With exact (FP64) coefficients in the oracle, order 2 still meets the bar because its
-    balanced pair b = (b0, -b0) is exact in float32; order 4 shows the DC sensitivity."""
+    """The reconstruction amplifies an offset in the filter's zero-frequency response by about
+    N.  With FP64 balanced coefficients (sum(b) = 0) the plan filters in first-difference form
+    and meets the bar at orders 2 and 4.  Fed float32-rounded coefficients (sum(b) a few ulps
+    off zero, so the plain form), it still matches an oracle given the same rounded values."""
     api = gpu_lib
     N, B = 512, 1
     P = _phantom_lino(N, B, seed=N)
-    errs = {}
     for order in (2, 4):
-        b64, a64 = _coef64(order)
-        with api.fbp_plan(N, B, b64, a64) as plan:
-            got = api.fbp_reconstruct(plan, P.cuda())
-            torch.cuda.synchronize()
-        ref = O.fbp_fht(P.to(torch.float64), torch.tensor(b64), torch.tensor(a64))
-        errs[order] = _rel_rmse(got, ref)
-    assert errs[2] < RTOL_RMSE
-    assert errs[4] < 2e-4
+        for coef in (_coef, _coef32):
+            b, a = coef(order)
+            with api.fbp_plan(N, B, b, a) as plan:
+                got = api.fbp_reconstruct(plan, P.cuda())
+                torch.cuda.synchronize()
+            ref = O.fbp_fht(P.to(torch.float64), torch.tensor(b), torch.tensor(a))
+            assert _rel_rmse(got, ref) < RTOL_RMSE, (order, coef.__name__)
+
+
+def test_numerator_form_switch_makes_graphs_stale(gpu_lib):
+    """Coefficients that change between balanced and unbalanced switch the numerator form,
+    which a captured graph has compiled in: its launch is refused until it is captured again.
+    An update that keeps the form is seen by the graph."""
+    api = gpu_lib
+    N, B = 256, 1
+    P = _phantom_lino(N, B, seed=3).cuda()
+    b, a = _coef(4)
+    with api.fbp_plan(N, B, b, a) as plan:
+        img = torch.empty(B, N, N, device="cuda")
+        g = api.fbp_graph_create([plan], [P], [img])
+        b2 = b * 1.5                                       # still balanced
+        api.fbp_plan_set_coefficients(plan, b2, a)
+        g.launch()
+        torch.cuda.synchronize()
+        ref = O.fbp_fht(P.cpu().to(torch.float64), torch.tensor(b2), torch.tensor(a))
+        assert _rel_rmse(img, ref) < RTOL_RMSE
+        b3 = b2.copy()
+        b3[0] += 1e-3                                      # unbalanced: plain form
+        api.fbp_plan_set_coefficients(plan, b3, a)
+        with pytest.raises(api.FbpError) as e:
+            g.launch()
+        assert e.value.code == -1
+        g.close()
+        got = api.fbp_reconstruct(plan, P)
+        torch.cuda.synchronize()
+        ref = O.fbp_fht(P.cpu().to(torch.float64), torch.tensor(b3), torch.tensor(a))
+        assert _rel_rmse(got, ref) < RTOL_RMSE
 
 
 def test_reconstruct_equals_filter_then_backproject(gpu_lib):

@@ -15,12 +15,14 @@ import oracle as O
 pytestmark = pytest.mark.gpu
 
 B2 = ([0.12372452, -0.12372452], [-0.17164439, -0.13239954])
+B4 = ([0.12493199, -0.122976, -0.0727046, 0.07074861],
+      [-0.17279862, -0.72164016, 0.07148985, 0.04270461])
 
 
-def _coef():
-    b, a = B2
-    return (np.array(b, np.float32).astype(np.float64),
-            np.array(a, np.float32).astype(np.float64))
+def _coef(order=2):
+    """Balanced ramp-like sets (sum(b) = 0): the plan filters them in first-difference form."""
+    b, a = B2 if order == 2 else B4
+    return np.array(b, np.float64), np.array(a, np.float64)
 
 
 def _lino(N, B, seed):
@@ -33,19 +35,22 @@ def _rel(got, ref):
     return float(torch.linalg.vector_norm(got - ref) / torch.linalg.vector_norm(ref))
 
 
-@pytest.mark.parametrize("N,B,schedules", [
-    (64, 2, [[6], [3, 3], [2, 2, 2], [1, 5], [5, 1]]),
-    (256, 2, [[4, 4, 0], [2, 6, 7], [4, 4, 7], [4, 4, 6], [3, 3, 2, 8], [1, 1, 6, 7]]),
-    (1024, 2, [[5, 5, 7], [5, 5, 9], [4, 6, 7], [3, 3, 4, 8], [2, 4, 4, 8], [5, 1, 4, 8]]),
-    (2048, 1, [[4, 4, 3, 8], [3, 5, 3, 8], [4, 3, 4, 9], [2, 3, 3, 3, 8]]),
-    (4096, 1, [[3, 4, 5, 8], [1, 6, 5, 8], [3, 5, 4, 8], [2, 5, 5, 9]]),
+@pytest.mark.parametrize("N,B,order,schedules", [
+    (64, 2, 2, [[6], [3, 3], [2, 2, 2], [1, 5], [5, 1]]),
+    (256, 2, 2, [[4, 4, 0], [2, 6, 7], [4, 4, 7], [4, 4, 6], [3, 3, 2, 8], [1, 1, 6, 7]]),
+    (1024, 2, 2, [[5, 5, 7], [5, 5, 9], [4, 6, 7], [3, 3, 4, 8], [2, 4, 4, 8], [5, 1, 4, 8]]),
+    (1024, 1, 4, [[4, 6, 7], [3, 3, 4, 8], [5, 1, 4, 8]]),
+    (2048, 1, 2, [[4, 4, 3, 8], [3, 5, 3, 8], [4, 3, 4, 9], [2, 3, 3, 3, 8]]),
+    (4096, 1, 2, [[3, 4, 5, 8], [1, 6, 5, 8], [3, 5, 4, 8], [2, 5, 5, 9]]),
+    (4096, 1, 4, [[3, 4, 5, 8], [1, 6, 5, 8], [3, 5, 4, 8]]),
 ])
-def test_schedules_are_bit_identical(gpu_lib, N, B, schedules):
+def test_schedules_are_bit_identical(gpu_lib, N, B, order, schedules):
     """Every listed schedule is one the kernels can run (last entry: log2 of the column-tile
-    width, 0 = keep; below N = 256 there are no column tiles)."""
+    width, 0 = keep; below N = 256 there are no column tiles).  Order 4 at N = 4096 runs pass
+    0 of 1, 2 and 3 levels on the two-wave first-pass kernel."""
     api = gpu_lib
     P = _lino(N, B, seed=N)
-    with api.fbp_plan(N, B, *_coef()) as plan:
+    with api.fbp_plan(N, B, *_coef(order)) as plan:
         ref = api.fbp_reconstruct(plan, P).clone()
         bp_ref = api.fht_backproject(plan, P).clone()
         fwd_ref = api.fht_forward(plan, ref).clone()

@@ -170,3 +170,27 @@ def test_window_covers_support_disc(N, disc):
     start = (N - 1 - torch.arange(N)) // 2 - N // 2
     assert torch.equal(start % N, sig)
     assert (lo >= start).all() and (hi <= start + N - 1).all()
+
+
+@pytest.mark.parametrize("order", [2, 3, 4, 8])
+def test_balanced_numerator_difference_form(order):
+    """A numerator with sum(b) = 0 factors as B(z) = (1 - z^-1) C(z) with c_k = b_0 + .. + b_k
+    (k < K - 1), the form the kernels take for such filters: filtering the first difference
+    d[i] = x[i] - x[i-1] (zero before the window) by C and A gives the causal recursion of
+    eq 9, and d'[i] = x[i] - x[i+1] gives the anticausal one (eq 13).  Zero response at zero
+    frequency: a constant row gives an output that vanishes once the start transient decays."""
+    g = np.random.default_rng(order)
+    a = torch.tensor(np.poly(g.uniform(-0.7, 0.7, size=order))[1:])
+    b = torch.tensor(g.normal(size=order))
+    b = b - b.mean()
+    c = torch.cumsum(b, 0)[:-1]
+    x = torch.tensor(g.normal(size=(3, 200)))
+    d = x - torch.nn.functional.pad(x, (1, 0))[:, :-1]
+    yc = O.iir_causal(x, b, a)
+    assert torch.allclose(O.iir_causal(d, c, a), yc, rtol=0, atol=1e-12 * float(yc.abs().max()))
+    da = x - torch.nn.functional.pad(x, (0, 1))[:, 1:]
+    ya = O.iir_anticausal(x, b, a)
+    assert torch.allclose(O.iir_anticausal(da, c, a), ya, rtol=0,
+                          atol=1e-12 * float(ya.abs().max()))
+    flat = O.iir_pair(torch.ones(1, 400, dtype=torch.float64), b, a)[0]
+    assert float(flat[150:250].abs().max()) < 1e-9

@@ -57,13 +57,14 @@ typedef struct {
                          divide 4N and be <= 64                                               */
   const double* b;    /* host [groups][order]: feed-forward b_0..b_{K-1} (eq 9); the causal
                          and the anticausal pass share them (Sec. 3)                          */
-  const double* a;    /* host [groups][order]: feedback a_1..a_K (eq 9).  The kernels hold b
-                         and a as float32 (rounded to nearest on upload).  When every group's
-                         b sums to zero (|sum b| <= 1e-12 sum |b|, the zero response at zero
-                         frequency that the ramp of eq 6 has) and K >= 2, they hold instead
-                         the cumulative sums c_k = b_0 + .. + b_k (k < K - 1, summed in double)
-                         and filter the first difference of each row: B(z) = (1 - z^-1) C(z),
-                         so the float32 filter keeps that zero exactly                         */
+  const double* a;    /* host [groups][order]: feedback a_1..a_K (eq 9).  The kernels hold a
+                         as float32 (rounded to nearest on upload).  For K >= 2 they take the
+                         numerator as B(z) = (1 - z^-1) C(z) + s: float32 taps
+                         c_k = -(b_{k+1} + .. + b_{K-1}) (summed in double) applied to the first
+                         difference of each row, plus s = sum(b) times the sample.  A group
+                         whose b sums to zero (|sum b| <= 1e-12 sum |b|: the zero response at
+                         zero frequency that the ramp of eq 6 has) gets s = 0 exactly, so the
+                         float32 filter keeps that zero exactly                                */
   uint32_t flags;     /* FBP_* flags above                                                    */
   void* stream;       /* hipStream_t used by every call (NULL = default stream)               */
 } fbp_plan_desc;
@@ -85,8 +86,9 @@ int fbp_plan_set_stream(fbp_plan_t plan, void* stream);
 
 /* Replace the recursive-filter coefficients (host arrays shaped as in the description).
  * Synchronises the plan's stream, checks stability, uploads.  Used by the learned filter.
- * Graphs captured on the plan keep working unless the numerator form changes (the new b
- * balanced where the old was not, or the reverse); then they refuse to launch (FBP_EINVAL). */
+ * Graphs captured on the plan keep working unless the numerator form changes (every group's
+ * new b balanced where some old one was not, or the reverse: the kernels then drop or add the
+ * remainder term s); such graphs refuse to launch (FBP_EINVAL) and must be captured again. */
 int fbp_plan_set_coefficients(fbp_plan_t plan, const double* b, const double* a);
 
 /* Row filter alone (Sec. 3, eq 12-13): every linogram row (b, q, t) is read over its window

@@ -86,7 +86,7 @@ __device__ void load_tile(const PassArgs& A, float* S, int b, int q, int row0) {
   }
 }
 
-// ---- first-difference numerator (DIFF filters) ----------------------------------------------
+// ---- first-difference numerator (orders K >= 2) -----------------------------------------------
 // On entry xc[k] = x[base - 1 - k] and xa[k] = x[base + L + k] for k < K - 1 (zero outside the
 // window).  Rearranged into the difference history: xc[k] = d[base - 1 - k] for k < K - 2 (the
 // slot K - 2 is shifted out before it is read) and xc[K - 1] = x[base - 1], the sample the next
@@ -130,14 +130,16 @@ __device__ __forceinline__ void diff_step(float* xc, float* xa, float xi, float 
 // run from the end of the window.  Inputs are re-read from LDS in each sweep (only a K-sample
 // sliding window is held), the output of the chunk is accumulated in registers.
 //
-// DIFF: the numerator is taken in first-difference form, B(z) = (1 - z^-1) C(z) with taps
-// c_k = b_0 + ... + b_k (k < K - 1; the plan uses it when every group has sum(b) = 0).  Each
-// recursion then filters d[i] = x[i] - x[i-1] (anticausal: x[i] - x[i+1]) by C, and a
-// float32 filter keeps the exactly zero response at zero frequency that the ramp has (eq 6):
-// rounding b_k c_t to float32 one tap at a time would leave sum_k b_k c_t a few ulps off zero,
-// an offset per row that the back projection sums over ~N rows.
-template <int L, int K, bool DIFF = false>
+// Orders K >= 2 take the numerator in first-difference form, B(z) = (1 - z^-1) C(z) + s with
+// taps c_k = -(b_{k+1} + ... + b_{K-1}) (k < K - 1) and s = sum(b): each recursion filters
+// d[i] = x[i] - x[i-1] (anticausal: x[i] - x[i+1]) by C and, when REM, adds s x[i].  For a
+// balanced numerator (sum(b) = 0) there is no remainder, and the float32 filter keeps the
+// exactly zero response at zero frequency that the ramp has (eq 6); otherwise that response is
+// s c_t rounded once.  Rounding b_k c_t to float32 one tap at a time would leave sum_k b_k c_t
+// a few ulps off its value, an offset per row that the back projection sums over ~N rows.
+template <int L, int K, bool REM = false>
 __device__ void filter_tile(const PassArgs& A, float* S, int q, int row0) {
+  constexpr bool DIFF = K >= 2;
   int tid = threadIdx.x;
   asm volatile("" : "+v"(tid));   // recomputed per call (keeps loop-invariant addresses out of
                                   // registers in the persistent kernel)
@@ -147,7 +149,7 @@ __device__ void filter_tile(const PassArgs& A, float* S, int q, int row0) {
   const int t = row0 + r;
   const int g = ((q * N + t) * A.groups) / (4 * N);
   const float* cf = A.coef + (size_t)g * A.coef_stride;
-  const float* cb = DIFF ? cf + A.coef_stride - K : cf;   // C's taps sit at the table's end
+  const float* cb = DIFF ? cf + A.coef_stride - K : cf;   // C's taps and s at the table's end
   int sig = A.sigma[t];
   const float ct = A.scale[t];
   // the row factor c_t scales the numerator: the recursion then yields c_t y directly
@@ -193,6 +195,10 @@ __device__ void filter_tile(const PassArgs& A, float* S, int q, int row0) {
     float ac = 0.f, aa = 0.f;
     if constexpr (DIFF) {
       diff_step<K>(xc, xa, in(base + i), in(base + j));
+      if constexpr (REM) {       // the remainder s x[i] first
+        ac = bk[K - 1] * xc[K - 1];
+        aa = bk[K - 1] * xa[K - 1];
+      }
 #pragma unroll
       for (int k = 0; k < K - 1; ++k) {
         ac = fmaf(bk[k], xc[k], ac);
@@ -306,11 +312,12 @@ __device__ void filter_tile(const PassArgs& A, float* S, int q, int row0) {
 // `step_hook(s)` runs at the top of recursion step s (the caller uses it to issue the next
 // tile's loads a few at a time, so the texture unit takes them while the ALUs work).
 // WIDE: rows of 128 chunks over two waves (the row length 4096); otherwise C <= 64.
-// DIFF: the first-difference numerator of filter_tile.
-template <int K, bool WIDE, bool DIFF, typename Hook>
+// The numerator forms of filter_tile (first difference for K >= 2, remainder when REM).
+template <int K, bool WIDE, bool REM, typename Hook>
 __device__ bool filter_tile_aligned(const PassArgs& A, float* S, float* xs, int q, int row0,
                                     float ct, Hook&& step_hook) {
   constexpr int L = 32;
+  constexpr bool DIFF = K >= 2;
   int tid = threadIdx.x;
   asm volatile("" : "+v"(tid));
   const int C = 1 << A.log2c;
@@ -319,7 +326,7 @@ __device__ bool filter_tile_aligned(const PassArgs& A, float* S, float* xs, int 
   const int t = row0 + r;
   const int g = __builtin_amdgcn_readfirstlane(((q * N + t) * A.groups) / (4 * N));
   cfloat* cf = as_constant(A.coef + (size_t)g * A.coef_stride);
-  cfloat* cb = DIFF ? cf + (A.coef_stride - K) : cf;   // C's taps sit at the table's end
+  cfloat* cb = DIFF ? cf + (A.coef_stride - K) : cf;   // C's taps and s at the table's end
   // the row factor c_t scales the numerator (per lane: a wave holds 64 / C rows)
   float bk[K], ak[K];
 #pragma unroll
@@ -367,6 +374,10 @@ __device__ bool filter_tile_aligned(const PassArgs& A, float* S, float* xs, int 
     float ac = 0.f, aa = 0.f;
     if constexpr (DIFF) {
       diff_step<K>(xc, xa, rp[i], rp[j]);
+      if constexpr (REM) {       // the remainder s x[i] first
+        ac = bk[K - 1] * xc[K - 1];
+        aa = bk[K - 1] * xa[K - 1];
+      }
 #pragma unroll
       for (int k = 0; k < K - 1; ++k) {
         ac = fmaf(bk[k], xc[k], ac);
@@ -1153,17 +1164,17 @@ __device__ void run_levels(const PassArgs& A, float* S) {
   }
 }
 
-template <int L, int K, bool STREAM, bool DIFF = false>
+template <int L, int K, bool STREAM, bool REM = false>
 __device__ void process_class(const PassArgs& A, float* S, int b, int q, int row0) {
   load_tile<L>(A, S, b, q, row0);
   __syncthreads();
-  if constexpr (K > 0) filter_tile<L, K, DIFF>(A, S, q, row0);
+  if constexpr (K > 0) filter_tile<L, K, REM>(A, S, q, row0);
   run_levels<L, STREAM>(A, S);
 }
 
 // Passes that keep the four classes apart: the first and middle passes of the back projection,
 // every pass of the forward transform, and the filter alone (OUT_SAME).
-template <int L, int K, bool STREAM, bool DIFF = false>
+template <int L, int K, bool STREAM, bool REM = false>
 __global__ void __launch_bounds__(1024) fht_rows_kernel(PassArgs A) {
   extern __shared__ float S[];
   const int T = blockDim.x, tid = threadIdx.x;
@@ -1184,7 +1195,7 @@ __global__ void __launch_bounds__(1024) fht_rows_kernel(PassArgs A) {
     v = tile & ((1 << vbits) - 1);
     row0 = (j << A.k_hi) + (v << F);
   }
-  process_class<L, K, STREAM, DIFF>(A, S, b, q, row0);
+  process_class<L, K, STREAM, REM>(A, S, b, q, row0);
 
   float* dst = A.out + (size_t)(b * 4 + q) * N * N;
   if (A.out_mode == OUT_SAME) {
@@ -1228,7 +1239,7 @@ __global__ void __launch_bounds__(1024) fht_rows_kernel(PassArgs A) {
 // pair in the image frame (eq 20-22).  OUT_IMG_V: classes 0 and 1 give image rows j R .. j R +
 // R - 1, image[y][x] = c0[y][x] + c1[y][N-1-x].  OUT_IMG_H: classes 2 and 3 give image columns
 // j R .. j R + R - 1, image[y][x] += c2[x][y] + c3[x][N-1-y] (launched after OUT_IMG_V).
-template <int L, int K, bool STREAM, bool DIFF = false>
+template <int L, int K, bool STREAM, bool REM = false>
 __global__ void __launch_bounds__(1024) fht_combine_kernel(PassArgs A) {
   extern __shared__ float S[];
   const int T = blockDim.x, tid = threadIdx.x;
@@ -1241,7 +1252,7 @@ __global__ void __launch_bounds__(1024) fht_combine_kernel(PassArgs A) {
   const int qa = vpair ? 0 : 2;
   const int row0 = j * R;
   float keep[L];
-  process_class<L, K, STREAM, DIFF>(A, S, b, qa, row0);
+  process_class<L, K, STREAM, REM>(A, S, b, qa, row0);
 #pragma unroll
   for (int k = 0; k < L; ++k) {
     const int e = tid + k * T;
@@ -1250,7 +1261,7 @@ __global__ void __launch_bounds__(1024) fht_combine_kernel(PassArgs A) {
     keep[k] = S[lds_at(brev_bits(i, F), c, A.rs, A.log2l)];
   }
   __syncthreads();
-  process_class<L, K, STREAM, DIFF>(A, S, b, qa + 1, row0);
+  process_class<L, K, STREAM, REM>(A, S, b, qa + 1, row0);
   float* img = A.out + (size_t)b * N * N;
   if (vpair) {
 #pragma unroll
@@ -1309,7 +1320,7 @@ __device__ __forceinline__ float4 load4_rotated(const float* row, int x, int o, 
 // the second half goes out before the levels; levels 1 .. F - 1 run as radix-4 stages (an odd
 // one streams first), the last of which stores the tile to HBM itself.  The loads of the next
 // tile are in flight through all of it.
-template <int L, int K, int NBLK, bool WIDE = false, bool DIFF = false>
+template <int L, int K, int NBLK, bool WIDE = false, bool REM = false>
 __global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
   extern __shared__ float S[];
   const int T = blockDim.x, tid = threadIdx.x;
@@ -1403,7 +1414,7 @@ __global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
       // the first half of the next tile's loads, one every 8 recursion steps (the last tile
       // of a block reloads itself instead of branching: no branch splits the filter's code)
       const int tn = more ? tl + (int)gridDim.x : tl;
-      level0 = filter_tile_aligned<K, WIDE, DIFF>(A, S, xs, q, row0, ct, [&](int s) {
+      level0 = filter_tile_aligned<K, WIDE, REM>(A, S, xs, q, row0, ct, [&](int s) {
         if ((s & 7) == 0) issue_one(tn, s >> 3);
       });
     } else {
@@ -2138,7 +2149,7 @@ hipError_t launch_kernel(Kern kern, const PassArgs& a, int blocks, int threads, 
   return hipGetLastError();
 }
 
-template <int L, int K, bool STREAM, bool DIFF>
+template <int L, int K, bool STREAM, bool REM>
 hipError_t launch_lksd(const PassArgs& a, int batch, hipStream_t stream) {
   const int N = 1 << a.log2n;
   const int R = 1 << a.log2r;
@@ -2147,20 +2158,20 @@ hipError_t launch_lksd(const PassArgs& a, int batch, hipStream_t stream) {
   const int tiles = N >> a.log2r;
   if (a.out_mode == OUT_IMG_V || a.out_mode == OUT_IMG_H) {
     if constexpr (L <= 32 || K == 0)
-      return launch_kernel(fht_combine_kernel<L, K, STREAM, DIFF>, a, batch * tiles, threads,
+      return launch_kernel(fht_combine_kernel<L, K, STREAM, REM>, a, batch * tiles, threads,
                            lds, stream);
     else
       return hipErrorInvalidValue;   // the filter runs in a combining pass only when N <= 128
   }
-  return launch_kernel(fht_rows_kernel<L, K, STREAM, DIFF>, a, batch * 4 * tiles, threads, lds,
+  return launch_kernel(fht_rows_kernel<L, K, STREAM, REM>, a, batch * 4 * tiles, threads, lds,
                        stream);
 }
 
-// First-difference numerator only for orders >= 2 (a balanced order-1 numerator is zero).
+// The remainder term of the first-difference numerator exists for orders >= 2 only.
 template <int L, int K, bool STREAM>
 hipError_t launch_lks(const PassArgs& a, int batch, hipStream_t stream) {
   if constexpr (K >= 2) {
-    if (a.diff) return launch_lksd<L, K, STREAM, true>(a, batch, stream);
+    if (a.rem) return launch_lksd<L, K, STREAM, true>(a, batch, stream);
   }
   return launch_lksd<L, K, STREAM, false>(a, batch, stream);
 }
@@ -2177,13 +2188,13 @@ hipError_t launch_lk(const PassArgs& a, int batch, hipStream_t stream) {
 
 }  // namespace
 
-// The first-pass kernel of order K, with the first-difference numerator when the plan's
-// coefficients allow it (orders >= 2).
+// The first-pass kernel of order K, with the numerator's remainder term when the plan's
+// coefficients have one (orders >= 2, unbalanced numerators).
 template <int L, int K, int NBLK, bool WIDE>
 hipError_t launch_first_k(const PassArgs& a, int grid, int threads, size_t lds,
                           hipStream_t stream) {
   if constexpr (K >= 2) {
-    if (a.diff)
+    if (a.rem)
       return launch_kernel(fht_first_kernel<L, K, NBLK, WIDE, true>, a, grid, threads, lds,
                            stream);
   }

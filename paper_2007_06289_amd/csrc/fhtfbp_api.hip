@@ -29,9 +29,10 @@ struct fbp_plan_s {
   unsigned generation = 0;    // bumped when the schedule or the numerator form changes
                               // (captured graphs go stale)
   std::vector<double> b, a;   // host copies [groups][order]
-  // every group's numerator sums to zero (zero response at zero frequency): the filters take
-  // it in first-difference form, which keeps that zero exact in float32
-  bool diff = false;
+  // the filters take the numerator in first-difference form (orders >= 2), which keeps a zero
+  // response at zero frequency exact in float32; `rem`: some group's sum(b) is not zero, so
+  // the kernels add the remainder term
+  bool rem = false;
   int coef_stride = 0;
   float* d_coef = nullptr;
   // N = 4096: the filter's own chunks are 64 samples (C = 64), while the persistent first pass
@@ -161,8 +162,27 @@ std::vector<int> backprojection_levels(int n, int fmax) {
   return v;
 }
 
+// A numerator whose taps sum to zero within their rounding in double: its remainder s is
+// taken as exactly zero.
+bool balanced_numerator(double sum, double mag) { return fabs(sum) <= 1e-12 * mag; }
+
+// Whether some group's numerator has a remainder (orders >= 2).
+bool numerator_remainder(const fbp_plan_s* p) {
+  if (p->order < 2) return false;
+  for (int g = 0; g < p->groups; ++g) {
+    double sum = 0.0, mag = 0.0;
+    for (int k = 0; k < p->order; ++k) {
+      sum += p->b[(size_t)g * p->order + k];
+      mag += fabs(p->b[(size_t)g * p->order + k]);
+    }
+    if (!balanced_numerator(sum, mag)) return true;
+  }
+  return false;
+}
+
 // One coefficient table for chunks of L samples: per group b[K], a[K], Phi^(L 2^j) for
-// j < kScanLevels, and the homogeneous responses h_k[0 .. L-1].
+// j < kScanLevels, the homogeneous responses h_k[0 .. L-1], and the first-difference
+// numerator's taps c[0 .. K-2] and remainder s.
 int fill_coefficients(const fbp_plan_s* p, int L, int stride, std::vector<float>& host) {
   const int K0 = p->order, G = p->groups;
   const int K = kernel_order(K0);   // taps K0..K-1 are zero
@@ -186,39 +206,32 @@ int fill_coefficients(const fbp_plan_s* p, int L, int stride, std::vector<float>
     homogeneous_table(ag.data(), K, L, hom.data());
     for (int i = 0; i < K * L; ++i)
       host[(size_t)g * stride + 2 * K + kScanLevels * K * K + i] = (float)hom[i];
-    // taps of C(z) with B(z) = (1 - z^-1) C(z) + sum(b) z^-(K-1): the cumulative sums of b in
-    // double, rounded once (used when every group's sum(b) is zero)
-    double c = 0.0;
-    for (int k = 0; k + 1 < K; ++k) {
-      c += bg[k];
-      host[(size_t)g * stride + stride - K + k] = (float)c;
+    // first-difference form B(z) = (1 - z^-1) C(z) + s: c_k = -(b_{k+1} + .. + b_{K-1}) for
+    // k < K - 1, s = sum(b) in the last slot, exactly zero for a balanced numerator (|sum(b)|
+    // within rounding of its taps in double); each summed in double and rounded once
+    double sum = 0.0, mag = 0.0;
+    for (int k = 0; k < K; ++k) {
+      sum += bg[k];
+      mag += fabs(bg[k]);
     }
+    const bool balanced = balanced_numerator(sum, mag);
+    double tail = 0.0;
+    for (int k = K - 2; k >= 0; --k) {
+      tail += bg[k + 1];
+      host[(size_t)g * stride + stride - K + k] = (float)(-tail);
+    }
+    host[(size_t)g * stride + stride - 1] = balanced ? 0.f : (float)sum;
   }
   return FBP_OK;
 }
 
-// Whether every group's numerator sums to zero, to rounding of its taps in double: then
-// B(z) = (1 - z^-1) C(z) exactly, and the filters run in first-difference form.
-bool balanced_numerators(const fbp_plan_s* p) {
-  if (p->order < 2) return false;
-  for (int g = 0; g < p->groups; ++g) {
-    double sum = 0.0, mag = 0.0;
-    for (int k = 0; k < p->order; ++k) {
-      sum += p->b[(size_t)g * p->order + k];
-      mag += fabs(p->b[(size_t)g * p->order + k]);
-    }
-    if (!(fabs(sum) <= 1e-12 * mag)) return false;
-  }
-  return true;
-}
-
 int upload_coefficients(fbp_plan_s* p) {
   std::vector<float> host, host32;
-  // the numerator form is compiled into the kernels a graph captured: a change makes such
+  // the remainder term is compiled into the kernels a graph captured: a change makes such
   // graphs stale, as a schedule change does
-  const bool diff = balanced_numerators(p);
-  if (diff != p->diff) p->generation += 1;
-  p->diff = diff;
+  const bool rem = numerator_remainder(p);
+  if (rem != p->rem) p->generation += 1;
+  p->rem = rem;
   int rc = fill_coefficients(p, 1 << p->log2l, p->coef_stride, host);
   if (rc == FBP_OK && p->d_coef32) rc = fill_coefficients(p, 32, p->coef_stride32, host32);
   if (rc != FBP_OK) return rc;
@@ -358,7 +371,7 @@ PassArgs base_args(const fbp_plan_s* p) {
   A.scale = p->d_scale;
   A.sigma = p->d_sigma;
   A.windowed = (p->flags & FBP_ZERO_WINDOW) ? 0 : 1;
-  A.diff = p->diff ? 1 : 0;
+  A.rem = p->rem ? 1 : 0;
   return A;
 }
 

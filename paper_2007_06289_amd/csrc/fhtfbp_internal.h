@@ -41,7 +41,8 @@ struct PassArgs {
   int groups;       // coefficient groups
   int coef_stride;  // floats per group in `coef`
   const float* coef;   // per group: b[K], a[K], Phi_j[K][K] for j < kScanLevels, h_k[L] for k < K,
-                       // c[K] (c_k = b_0 + .. + b_k for k < K - 1, c[K - 1] = 0)
+                       // c[K] (c_k = -(b_{k+1} + .. + b_{K-1}) for k < K - 1, c[K - 1] = sum(b)
+                       // or exactly 0 for a balanced numerator)
   const float* scale;  // [N] row factor c_t
   const int* sigma;    // [N] window start of row t
   int rs;              // LDS row stride in floats
@@ -50,7 +51,7 @@ struct PassArgs {
   int halo;            // column-tiled passes: extra columns loaded below the tile (>= 2^F - 1)
   int total_tiles;     // persistent passes: tiles over the whole batch
   int windowed;        // 1: rows start at the window start below, 0: at shift 0
-  int diff;            // 1: filter numerator in first-difference form (taps c; sum(b) = 0)
+  int rem;             // 1: the first-difference numerator has a remainder s x[i] (sum(b) != 0)
 };
 
 // Fourth word of a raw buffer resource on gfx9-family devices (32-bit data, no swizzle).

@@ -28,9 +28,10 @@ COEF = {
 
 def _coef(order, groups=1, seed=0, balanced=False):
     """FP64 coefficients, as the ABI takes them; both sides get the same values.  The fixed
-    sets of orders 2-4 have sum(b) = 0 (zero response at zero frequency, as the ramp), so the
-    plan runs them in first-difference form; random sets (orders 5-8, several groups) are
-    unbalanced unless `balanced`, which removes the mean of each group's b."""
+    sets of orders 2-4 have sum(b) = 0 (zero response at zero frequency, as the ramp): the
+    kernels' first-difference numerator then has no remainder term.  Random sets (orders 5-8,
+    several groups) are unbalanced, with a remainder, unless `balanced`, which removes the mean
+    of each group's b."""
     if order in COEF and groups == 1:
         b, a = COEF[order]
         return np.array(b), np.array(a)
@@ -48,8 +49,8 @@ def _coef(order, groups=1, seed=0, balanced=False):
 
 
 def _coef32(order, groups=1, seed=0, balanced=False):
-    """The same coefficients rounded to float32 (then unbalanced by rounding: the plan takes
-    them in the plain numerator form)."""
+    """The same coefficients rounded to float32 (unbalanced by the rounding: the kernels add
+    the remainder term)."""
     b, a = _coef(order, groups, seed, balanced)
     return b.astype(np.float32).astype(np.float64), a.astype(np.float32).astype(np.float64)
 
@@ -276,9 +277,10 @@ def test_reconstruct_flags_on_the_fused_first_pass(gpu_lib, N, flags):
 
 def test_coefficient_rounding_sensitivity(gpu_lib):
     """The reconstruction amplifies an offset in the filter's zero-frequency response by about
-    N.  With FP64 balanced coefficients (sum(b) = 0) the plan filters in first-difference form
-    and meets the bar at orders 2 and 4.  Fed float32-rounded coefficients (sum(b) a few ulps
-    off zero, so the plain form), it still matches an oracle given the same rounded values."""
+    N.  With FP64 balanced coefficients (sum(b) = 0) the first-difference numerator keeps that
+    response exactly zero, and the bar holds at orders 2 and 4.  Fed float32-rounded
+    coefficients (sum(b) a few ulps off zero: a remainder term s = sum(b), rounded once), it
+    matches an oracle given the same rounded values."""
     api = gpu_lib
     N, B = 512, 1
     P = _phantom_lino(N, B, seed=N)
@@ -293,9 +295,10 @@ def test_coefficient_rounding_sensitivity(gpu_lib):
 
 
 def test_numerator_form_switch_makes_graphs_stale(gpu_lib):
-    """Coefficients that change between balanced and unbalanced switch the numerator form,
-    which a captured graph has compiled in: its launch is refused until it is captured again.
-    An update that keeps the form is seen by the graph."""
+    """Coefficients that change between balanced and unbalanced add or drop the remainder term
+    of the numerator, which a captured graph has compiled in: its launch is refused until it
+    is captured again.  An update that keeps the form is seen by the graph.  A nearly balanced
+    numerator (sum(b) = 1e-3 b_0) still meets the bar: its remainder is rounded once."""
     api = gpu_lib
     N, B = 256, 1
     P = _phantom_lino(N, B, seed=3).cuda()
@@ -310,7 +313,7 @@ def test_numerator_form_switch_makes_graphs_stale(gpu_lib):
         ref = O.fbp_fht(P.cpu().to(torch.float64), torch.tensor(b2), torch.tensor(a))
         assert _rel_rmse(img, ref) < RTOL_RMSE
         b3 = b2.copy()
-        b3[0] += 1e-3                                      # unbalanced: plain form
+        b3[0] += 1e-3 * b3[0]                              # unbalanced: remainder term
         api.fbp_plan_set_coefficients(plan, b3, a)
         with pytest.raises(api.FbpError) as e:
             g.launch()

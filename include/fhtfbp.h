@@ -45,6 +45,12 @@ extern "C" {
                                  one more k_t, i.e. c_t = k_t^2 * w_t                      */
 #define FBP_ZERO_WINDOW   4u  /* filter every row over shifts 0..N-1 instead of the window
                                  centred on the row's central intercept                   */
+#define FBP_NO_SCRATCH    8u  /* allocate no inter-pass scratch: the plan then serves
+                                 fbp_reconstruct_noalloc (and one-pass sizes, N <= 128);
+                                 calls that need the plan's scratch give FBP_EINVAL         */
+
+/* Size of the fixed scratch array of fbp_reconstruct_noalloc, per device. */
+#define FBP_NOALLOC_SCRATCH_BYTES (256u << 20)
 
 typedef struct fbp_plan_s* fbp_plan_t;
 
@@ -111,6 +117,20 @@ int fht_forward(fbp_plan_t plan, const float* img, float* lino, int32_t batch);
  * fht_backproject, with the filter fused into the first back-projection pass (the linogram
  * is read once).  `lino` is not modified. */
 int fbp_reconstruct(fbp_plan_t plan, const float* lino, float* img, int32_t batch);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): fbp_reconstruct with its inter-pass scratch taken
+ * from a fixed array inside the library, FBP_NOALLOC_SCRATCH_BYTES per device, which each
+ * device holds from the library's load until the process ends, instead of from the plan.
+ * The call allocates nothing and records no timing events; create the plan beforehand (with
+ * FBP_NO_SCRATCH it holds no scratch of its own).  The batch runs in chunks of at most
+ * FBP_NOALLOC_SCRATCH_BYTES / (16 N^2 bytes x buffers) slices, buffers = 1 for a schedule of
+ * two passes and 2 for three or more; a size whose single slice needs more than the array
+ * (N = 4096) gives FBP_ERANGE before anything is launched.  Results are bit-identical to
+ * fbp_reconstruct.  Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (other streams, host threads or plans) race on it and must be serialised by the caller.
+ * FBP_EDEVICE if the array's address could not be resolved when the plan was made. */
+int fbp_reconstruct_noalloc(fbp_plan_t plan, const float* lino, float* img, int32_t batch);
 
 /* Gradient of a loss with respect to the recursive-filter coefficients, for learning them:
  * `lino` is the filter input and `grad_out` dL/d(fbp_filter output), both [batch][4][N][N].

@@ -31,6 +31,8 @@ FBP_ERANGE = -5
 FBP_NO_ROW_SCALE = 1
 FBP_INPUT_IS_FHT = 2
 FBP_ZERO_WINDOW = 4
+FBP_NO_SCRATCH = 8
+FBP_NOALLOC_SCRATCH_BYTES = 256 << 20
 
 FIT_DC_ZERO = 1
 
@@ -79,6 +81,7 @@ def load_library():
         "fht_backproject": ([vp, vp, vp, i32], ctypes.c_int),
         "fht_forward": ([vp, vp, vp, i32], ctypes.c_int),
         "fbp_reconstruct": ([vp, vp, vp, i32], ctypes.c_int),
+        "fbp_reconstruct_noalloc": ([vp, vp, vp, i32], ctypes.c_int),
         "fbp_fit_ramp_iir": ([i32, i32, u32, dp, dp, dp], ctypes.c_int),
         "fbp_direct_parallel": ([vp, vp, vp, i32, i32, i32, i32, vp], ctypes.c_int),
         "fbp_direct_filter": ([vp, vp, i32, i32, i32, vp], ctypes.c_int),
@@ -304,6 +307,18 @@ def fbp_reconstruct(plan: Plan, lino: torch.Tensor, img: torch.Tensor | None = N
     pi = _dev_ptr(img, "img", (B, plan.n, plan.n))
     plan.bind_stream()
     _check(load_library().fbp_reconstruct(plan.handle, pl, pi, B), "fbp_reconstruct")
+    return img
+
+
+def fbp_reconstruct_noalloc(plan: Plan, lino: torch.Tensor, img: torch.Tensor):
+    """fbp_reconstruct with the library's fixed scratch array: the C call allocates nothing
+    (the caller passes the output).  [B,4,N,N] -> [B,N,N]."""
+    B = _batch_of(lino, 3, "lino")
+    pl = _dev_ptr(lino, "lino", (B, 4, plan.n, plan.n))
+    pi = _dev_ptr(img, "img", (B, plan.n, plan.n))
+    plan.bind_stream()
+    _check(load_library().fbp_reconstruct_noalloc(plan.handle, pl, pi, B),
+           "fbp_reconstruct_noalloc")
     return img
 
 

@@ -61,7 +61,34 @@ struct fbp_graph_s {
   std::vector<std::pair<fbp_plan_s*, unsigned>> plans;   // distinct plans, schedule generation
 };
 
+// ---- fixed scratch of fbp_reconstruct_noalloc ----------------------------------------------
+// The inter-pass intermediate of the no-allocation entry point lives in this array, one copy
+// per device, held from the code object's load until the process ends.  Host code never uses
+// the array's name as an address: fbp_plan resolves each device's copy once, with that device
+// current, and the entry point passes that address to the kernels.
+constexpr size_t kNoAllocScratchFloats = FBP_NOALLOC_SCRATCH_BYTES / sizeof(float);
+static __device__ __align__(256) float scratch[kNoAllocScratchFloats];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+float* g_noalloc_ptr[kMaxDevices] = {};
+
+void resolve_noalloc_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (g_noalloc_ptr[device]) return;
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) == hipSuccess && ptr)
+    g_noalloc_ptr[device] = static_cast<float*>(ptr);
+}
+
+float* noalloc_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  return g_noalloc_ptr[device];
+}
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 int ilog2(int v) {
@@ -397,11 +424,17 @@ bool first_pass_args(const fbp_plan_s* p, PassArgs& A) {
 
 // Run the transposed FHT passes.  forward: image -> linogram through the mirrored transform;
 // otherwise linogram -> image (with the filter fused into the first pass when `filter`).
+// The intermediate of `batch` slices ping-pongs through scratch[0] and scratch[1] (NULL for
+// the plan's own buffers); a buffer the schedule needs and does not have gives FBP_EINVAL
+// before anything is launched.
 int run_passes(fbp_plan_s* p, const float* in, float* out, int batch, bool forward,
-               bool filter, const Issue& is) {
+               bool filter, const Issue& is, float* const* scratch = nullptr) {
   if (batch == 0) return FBP_OK;
   const std::vector<int>& levels = forward ? p->fwd_levels : p->levels;
   const int P = (int)levels.size();
+  float* const* bufs = scratch ? scratch : p->d_scratch;
+  for (int i = 0; i < scratch_needed(levels.size()); ++i)
+    if (!bufs[i]) return FBP_EINVAL;
   int k = p->log2n;
   const float* src = in;
   for (int pi = 0; pi < P; ++pi) {
@@ -423,7 +456,7 @@ int run_passes(fbp_plan_s* p, const float* in, float* out, int batch, bool forwa
       A.halo = std::max(4, 1 << F);
     }
     if (!last) {
-      float* dst = p->d_scratch[pi & 1];
+      float* dst = bufs[pi & 1];
       A.out = dst;
       A.out_mode = OUT_ROWS;
       if (cols) {
@@ -672,7 +705,8 @@ int fbp_plan(const fbp_plan_desc* d, fbp_plan_t* out) {
   if (d->order < 1 || d->order > kMaxOrder) return FBP_EINVAL;
   if (d->groups < 1 || d->groups > 64 || (4 * d->n) % d->groups != 0) return FBP_EINVAL;
   if (!d->a || !d->b) return FBP_EINVAL;
-  if (d->flags & ~(FBP_NO_ROW_SCALE | FBP_INPUT_IS_FHT | FBP_ZERO_WINDOW)) return FBP_EINVAL;
+  if (d->flags & ~(FBP_NO_ROW_SCALE | FBP_INPUT_IS_FHT | FBP_ZERO_WINDOW | FBP_NO_SCRATCH))
+    return FBP_EINVAL;
   const int K = d->order, G = d->groups;
   for (int i = 0; i < G * K; ++i)
     if (!isfinite(d->a[i]) || !isfinite(d->b[i])) return FBP_EUNSTABLE;
@@ -696,6 +730,9 @@ int fbp_plan(const fbp_plan_desc* d, fbp_plan_t* out) {
     delete p;
     return FBP_EDEVICE;
   }
+  // set-up of fbp_reconstruct_noalloc on this device (its fixed scratch array's address),
+  // with the device current; a failure shows only in that call (FBP_EDEVICE)
+  resolve_noalloc_scratch(p->device);
   // filter chunks: C = min(64, N / 32) chunks of L = N / C samples per row (C = 1, L = N
   // below N = 32); C never exceeds a wavefront so a row's scan stays in one wave
   const int N = p->n;
@@ -759,7 +796,9 @@ int fbp_plan(const fbp_plan_desc* d, fbp_plan_t* out) {
   }
   const size_t per_class = (size_t)N * N;
   p->scratch_floats = (size_t)p->max_batch * 4 * per_class;
-  const int nscratch = scratch_needed(std::max(p->levels.size(), p->fwd_levels.size()));
+  const int nscratch = (p->flags & FBP_NO_SCRATCH)
+                           ? 0
+                           : scratch_needed(std::max(p->levels.size(), p->fwd_levels.size()));
   bool ok = hipMalloc(&p->d_coef, (size_t)G * p->coef_stride * sizeof(float)) == hipSuccess &&
             (p->coef_stride32 == 0 ||
              hipMalloc(&p->d_coef32, (size_t)G * p->coef_stride32 * sizeof(float)) ==
@@ -881,6 +920,29 @@ int fbp_reconstruct(fbp_plan_t p, const float* lino, float* img, int32_t batch) 
   if (batch == 0) return FBP_OK;
   if (!lino || !img || !aligned16(lino) || !aligned16(img)) return FBP_EINVAL;
   return run_passes(p, lino, img, batch, false, true, plan_issue(p));
+}
+
+int fbp_reconstruct_noalloc(fbp_plan_t p, const float* lino, float* img, int32_t batch) {
+  int rc = check_batch(p, batch);
+  if (rc != FBP_OK) return rc;
+  if (batch == 0) return FBP_OK;
+  if (!lino || !img || !aligned16(lino) || !aligned16(img)) return FBP_EINVAL;
+  float* base = noalloc_scratch(p->device);
+  if (!base) return FBP_EDEVICE;
+  const size_t n2 = (size_t)p->n * p->n;
+  const size_t per_buffer = 4 * n2;                 // floats of one slice's intermediate
+  const int nbuf = scratch_needed(p->levels.size());
+  const size_t chunk = nbuf ? kNoAllocScratchFloats / (nbuf * per_buffer) : (size_t)batch;
+  if (chunk == 0) return FBP_ERANGE;                // one slice needs more than the array
+  const Issue is{p->stream, false};                 // no timing events: they would allocate
+  for (int b0 = 0; b0 < batch; b0 += (int)chunk) {
+    const int nb = (int)std::min<size_t>(chunk, (size_t)(batch - b0));
+    float* bufs[2] = {base, base + (size_t)nb * per_buffer};
+    rc = run_passes(p, lino + (size_t)b0 * per_buffer, img + (size_t)b0 * n2, nb, false, true,
+                    is, bufs);
+    if (rc != FBP_OK) return rc;
+  }
+  return FBP_OK;
 }
 
 int fht_forward(fbp_plan_t p, const float* img, float* lino, int32_t batch) {
@@ -1071,7 +1133,7 @@ int fbp_plan_set_schedule(fbp_plan_t p, const int32_t* levels, int32_t passes, i
   if (rc != FBP_OK) return rc;
   const int have = scratch_needed(std::max(p->levels.size(), p->fwd_levels.size()));
   const int need = scratch_needed(lv.size());
-  if (need > have) {
+  if (need > have && !(p->flags & FBP_NO_SCRATCH)) {
     if (hipStreamSynchronize(p->stream) != hipSuccess) return FBP_EDEVICE;
     for (int i = 0; i < need; ++i) {
       if (p->d_scratch[i]) continue;

@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--no-direct", action="store_true", help="skip the direct-FBP comparator")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-slices", type=int, default=96)
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-filter leg (128 + 16 noisy slices of N = 1024)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (for scaling the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -309,6 +311,23 @@ def mixed_batch(F, I, b, a, reps: int = 10):
             "graph_equals_eager": bool(same)}
 
 
+def learned_leg(n: int) -> dict:
+    """The learned parts at their stated shape: 128 training and 16 held-out slices of
+    30-ellipse phantoms with Poisson noise at 1e4 photons, order-4 coefficients per 8 angle
+    groups plus the residual network, trained on the GPU with the library's kernels (300
+    steps); held-out relative RMSE against the direct FBP of the same data, and slices/s of the
+    plain method, the learned coefficients, and the learned coefficients plus the network, all
+    on the same 128-slice batch."""
+    from paper_2007_06289_amd import train_learned
+    t0 = time.perf_counter()
+    rep = train_learned.run(n=n, slices=128, holdout=16, steps=300, batch=8)
+    rep["leg_seconds"] = round(time.perf_counter() - t0, 1)
+    sp = rep["slices_per_s"]
+    rep["speed_ratio_learned_coefficients_vs_plain"] = round(
+        sp["learned_coefficients"] / sp["plain"], 4)
+    return rep
+
+
 def cpu_baseline(lino_cpu, b, a):
     """The FP64 oracle (as it stands) on a bounded sample of slices, on the host's cores."""
     import torch
@@ -482,6 +501,11 @@ def main():
     if not args.no_mixed:
         out["mixed_batch"] = mixed_batch(F, I, b, a)
         print(f"[bench] mixed batch {out['mixed_batch']}", file=sys.stderr, flush=True)
+
+    # ---- learned filter: 128 noisy slices of N = 1024, order 4 x 8 angle groups + network ------
+    if not args.no_learned:
+        out["learned"] = learned_leg(N)
+        print(f"[bench] learned {out['learned']}", file=sys.stderr, flush=True)
 
     # ---- CPU oracle on a bounded sample (also gives the FP32-vs-FP64 RMSE) ---------------------
     if not args.no_cpu:

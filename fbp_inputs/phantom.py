@@ -231,15 +231,23 @@ def parallel_sinogram(ells: EllipseSet, n: int, n_angles: int, *, n_det: int | N
     return _ellipse_line_integrals(p, nx, ny, r)
 
 
-def poisson_noisy(p: torch.Tensor, i0: float, seed: int, *, max_attenuation: float = 2.0):
+def poisson_noisy(p: torch.Tensor, i0: float, seed: int, *, max_attenuation: float = 2.0,
+                  on_device: bool = False):
     """Poisson-noised line integrals at ``i0`` incident photons per ray.
 
     Line integrals are scaled by mu = max_attenuation / max|p| into attenuations, photon
-    counts drawn as Poisson(i0 * exp(-mu p)) (seeded, on the CPU), floored at 1 count, and
-    converted back by -log(counts / i0) / mu.
+    counts drawn as Poisson(i0 * exp(-mu p)) (seeded, on the CPU; with ``on_device`` and a
+    GPU tensor, on the GPU from a generator of that device seeded the same way, a different
+    but equally reproducible draw), floored at 1 count, and converted back by
+    -log(counts / i0) / mu.
     """
-    g = _gen(seed)
-    pc = p.detach().to("cpu", torch.float64)
+    if on_device and p.is_cuda:
+        g = torch.Generator(device=p.device)
+        g.manual_seed(int(seed))
+        pc = p.detach().to(torch.float64)
+    else:
+        g = _gen(seed)
+        pc = p.detach().to("cpu", torch.float64)
     mu = max_attenuation / float(pc.abs().max().clamp_min(1e-30))
     lam = i0 * torch.exp(-mu * pc)
     counts = torch.poisson(lam, generator=g).clamp_min(1.0)

@@ -91,6 +91,7 @@ def load_library():
         "fbp_cnn_packed_elems": ([i32], ctypes.c_int32),
         "fbp_cnn_conv": ([i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, i32, i32, i32, i32, vp],
                          ctypes.c_int),
+        "fbp_cnn_forward": ([vp, vp, vp, vp, vp, vp, vp, vp, i32, i32, i32, vp], ctypes.c_int),
         "fbp_cnn_wgrad_partial_floats": ([i32, i32, i32, i32, i32], ctypes.c_int64),
         "fbp_cnn_wgrad": ([i32, i32, vp, vp, vp, vp, vp, vp, i32, i32, i32, vp], ctypes.c_int),
         "fbp_direct_backproject": ([vp, vp, i32, i32, i32, i32, vp], ctypes.c_int),
@@ -448,6 +449,26 @@ def fbp_cnn_conv(cin: int, cout: int, x: torch.Tensor, wpacked: torch.Tensor,
                                        _ptr(x) if cin == 16 else None, _ptr(wpacked), _ptr(bias),
                                        _ptr(mask), _ptr(resid), _ptr(o16), _ptr(o32),
                                        1 if relu else 0, B, H, W, _stream_ptr()), "fbp_cnn_conv")
+    return out
+
+
+def fbp_cnn_forward(x: torch.Tensor, p1: torch.Tensor, b1: torch.Tensor, p2: torch.Tensor,
+                    b2: torch.Tensor, p3: torch.Tensor, b3: torch.Tensor,
+                    out: torch.Tensor | None = None) -> torch.Tensor:
+    """The residual network at inference in one launch: [B,H,W] FP32 -> [B,H,W], weights packed
+    by fbp_cnn_pack."""
+    B, H, W = x.shape
+    _check_dev(x, "x", torch.float32)
+    if out is None:
+        out = torch.empty_like(x)
+    _check_dev(out, "out", torch.float32, (B, H, W))
+    for t, nm, dt in ((p1, "p1", torch.int16), (p2, "p2", torch.int16), (p3, "p3", torch.int16),
+                      (b1, "b1", torch.float32), (b2, "b2", torch.float32),
+                      (b3, "b3", torch.float32)):
+        _check_dev(t, nm, dt)
+    _check(load_library().fbp_cnn_forward(_ptr(x), _ptr(p1), _ptr(b1), _ptr(p2), _ptr(b2),
+                                          _ptr(p3), _ptr(b3), _ptr(out), B, H, W,
+                                          _stream_ptr()), "fbp_cnn_forward")
     return out
 
 

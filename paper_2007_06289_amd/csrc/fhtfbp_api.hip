@@ -1062,6 +1062,19 @@ int fbp_cnn_conv(int32_t cin, int32_t cout, const float* in32, const uint16_t* i
              : FBP_EDEVICE;
 }
 
+int fbp_cnn_forward(const float* img, const uint16_t* w1, const float* b1, const uint16_t* w2,
+                    const float* b2, const uint16_t* w3, const float* b3, float* out,
+                    int32_t batch, int32_t h, int32_t w, void* stream) {
+  if (batch < 0 || h < 1 || w < 1) return FBP_EINVAL;
+  if (batch == 0) return FBP_OK;
+  if (!img || !w1 || !b1 || !w2 || !b2 || !w3 || !b3 || !out) return FBP_EINVAL;
+  if (img == out) return FBP_EINVAL;   // blocks read a halo that other blocks write
+  return launch_cnn_fused(img, w1, b1, w2, b2, w3, b3, out, batch, h, w, (hipStream_t)stream) ==
+                 hipSuccess
+             ? FBP_OK
+             : FBP_EDEVICE;
+}
+
 int64_t fbp_cnn_wgrad_partial_floats(int32_t cin, int32_t cout, int32_t batch, int32_t h,
                                      int32_t w) {
   if (!cnn_shape_ok(cin, cout) || batch < 1 || h < 1 || w < 64 || (w % 64) != 0) return FBP_EINVAL;

@@ -154,6 +154,10 @@ hipError_t launch_cnn_wgrad(int cin, int cout, const float* dz32, const uint16_t
                             const float* in32, const uint16_t* in16, float* partial, float* out,
                             int batch, int H, int W, hipStream_t stream);
 int cnn_wgrad_rows();
+hipError_t launch_cnn_fused(const float* in, const uint16_t* w1, const float* b1,
+                            const uint16_t* w2, const float* b2, const uint16_t* w3,
+                            const float* b3, float* out, int batch, int H, int W,
+                            hipStream_t stream);
 
 // Direct FBP comparator kernels.
 hipError_t launch_direct_filter(const float* sino, float* work, int rows, int n_det,

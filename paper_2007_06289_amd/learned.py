@@ -66,6 +66,15 @@ class ResidualCNN(torch.autograd.Function):
 
 
 def residual_cnn(x0: torch.Tensor, w: dict) -> torch.Tensor:
+    """The network on [B, H, W] images.  When no gradient is needed, one fused launch
+    (``fbp_cnn_forward``: hidden activations stay on chip, same result bit for bit); otherwise
+    the layer-by-layer form whose activations the backward pass reuses."""
+    needs_grad = torch.is_grad_enabled() and (
+        x0.requires_grad or any(v.requires_grad for v in w.values()))
+    if not needs_grad:
+        return api.fbp_cnn_forward(x0.contiguous(), api.fbp_cnn_pack(w["w1"]), w["b1"],
+                                   api.fbp_cnn_pack(w["w2"]), w["b2"], api.fbp_cnn_pack(w["w3"]),
+                                   w["b3"])
     return ResidualCNN.apply(x0, w["w1"], w["b1"], w["w2"], w["b2"], w["w3"], w["b3"])
 
 

@@ -36,6 +36,80 @@ def _timeit(fn, reps=5):
     return (time.perf_counter() - t) / reps
 
 
+def run(n: int = 1024, slices: int = 128, holdout: int = 16, steps: int = 300, batch: int = 8,
+        i0: float = 1e4, order: int = 4, groups: int = 8, seed: int = 5, out: str | None = None,
+        log=None) -> dict:
+    """Build the noisy data and its direct-FBP target on the GPU, train, evaluate on the
+    held-out slices, time the three reconstructions on the training batch; returns the report
+    (and saves the model when `out` is given)."""
+    log = log or (lambda s: None)
+    N, S, H = n, slices, holdout
+    dev = "cuda"
+
+    t0 = time.perf_counter()
+    ells = I.random_ellipses(N, 30, seed=seed, batch=S + H)
+    clean = I.linogram(ells, N, device=dev, dtype=torch.float32, chunk=16)
+    noisy = I.poisson_noisy(clean, i0, seed=seed + 1, on_device=True).contiguous()
+    del clean
+    target = torch.empty((S + H, N, N), device=dev)
+    for i in range(0, S + H, 16):
+        api.fbp_direct_linogram(noisy[i:i + 16], target[i:i + 16])
+    torch.cuda.synchronize()
+    mask = I.support_mask(N, device=dev)
+    data_s = time.perf_counter() - t0
+    log(f"data: {S}+{H} slices of N={N}, I0={i0:g}, built in {data_s:.1f} s")
+
+    tr, te = slice(0, S), slice(S, S + H)
+    b0, a0, fit_err = api.fbp_fit_ramp_iir(order, min(N, 512), dc_zero=True)
+    plain = api.fbp_plan(N, max(S, H), np.tile(b0, (groups, 1)), np.tile(a0, (groups, 1)))
+    e_plain = L.relative_rmse(plain, noisy[te], target[te], mask)
+    log(f"plain order-{order} FHT-FBP: held-out relative RMSE {e_plain:.4f}")
+
+    model = L.LearnedFBP(N, max(batch, H, 16), order=order, groups=groups, cnn=True,
+                         fit_length=min(N, 512))
+    t1 = time.perf_counter()
+    hist = L.train(model, noisy[tr], target[tr], mask, steps=steps, batch=batch, log=log)
+    train_s = time.perf_counter() - t1
+    e_learned = L.relative_rmse(model, noisy[te], target[te], mask)
+    # learned coefficients alone (no network): same cost as the plain method
+    b, a = model.coefficients()
+    coef_only = api.fbp_plan(N, max(S, H), b.detach().numpy(), a.detach().numpy())
+    e_coef = L.relative_rmse(coef_only, noisy[te], target[te], mask)
+    log(f"learned: coefficients only {e_coef:.4f}, with network {e_learned:.4f} "
+        f"(trained {steps} steps in {train_s:.1f} s)")
+
+    x = noisy[tr]
+    img = torch.empty((S, N, N), device=dev)
+    t_plain = _timeit(lambda: api.fbp_reconstruct(plain, x, img))
+    t_coef = _timeit(lambda: api.fbp_reconstruct(coef_only, x, img))
+    cnn_w = {k: v.detach() for k, v in model.cnn.items()}
+    with torch.no_grad():
+        t_full = _timeit(lambda: L.residual_cnn(api.fbp_reconstruct(coef_only, x, img), cnn_w))
+    if out:
+        model.save(out)
+    rep = {
+        "workload": f"{S} noisy slices (I0={i0:g}) N={N}, order {order} x "
+                    f"{groups} angle groups, residual network 1-16-16-1; {H} held out",
+        "judge": "direct FBP of the same noisy linogram (exact ramp, exact line positions), "
+                 "fbp_direct_linogram on the GPU",
+        "rel_rmse_vs_direct_fbp": {"plain": round(e_plain, 5),
+                                   "learned_coefficients": round(e_coef, 5),
+                                   "learned_coefficients_and_network": round(e_learned, 5)},
+        "slices_per_s": {"plain": round(S / t_plain, 1),
+                         "learned_coefficients": round(S / t_coef, 1),
+                         "learned_coefficients_and_network": round(S / t_full, 1)},
+        "batch": S, "fit_rel_err": fit_err, "train_steps": steps,
+        "train_seconds": round(train_s, 1), "data_seconds": round(data_s, 1),
+        "final_train_loss": hist[-1],
+    }
+    if out:
+        rep["model"] = out
+    plain.close()
+    coef_only.close()
+    model.close()
+    return rep
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--n", type=int, default=1024)
@@ -50,65 +124,9 @@ def main(argv=None):
     ap.add_argument("--out", default="learned_model.pt")
     args = ap.parse_args(argv)
     log = lambda s: print(f"[learned] {s}", file=sys.stderr, flush=True)  # noqa: E731
-    N, S, H = args.n, args.slices, args.holdout
-    dev = "cuda"
-
-    t0 = time.perf_counter()
-    ells = I.random_ellipses(N, 30, seed=args.seed, batch=S + H)
-    clean = I.linogram(ells, N, device=dev, dtype=torch.float32, chunk=16)
-    noisy = I.poisson_noisy(clean, args.i0, seed=args.seed + 1).contiguous()
-    del clean
-    target = torch.empty((S + H, N, N), device=dev)
-    for i in range(0, S + H, 16):
-        api.fbp_direct_linogram(noisy[i:i + 16], target[i:i + 16])
-    torch.cuda.synchronize()
-    mask = I.support_mask(N, device=dev)
-    log(f"data: {S}+{H} slices of N={N}, I0={args.i0:g}, built in {time.perf_counter() - t0:.1f} s")
-
-    tr, te = slice(0, S), slice(S, S + H)
-    b0, a0, fit_err = api.fbp_fit_ramp_iir(args.order, min(N, 512), dc_zero=True)
-    plain = api.fbp_plan(N, max(S, H), np.tile(b0, (args.groups, 1)), np.tile(a0, (args.groups, 1)))
-    e_plain = L.relative_rmse(plain, noisy[te], target[te], mask)
-    log(f"plain order-{args.order} FHT-FBP: held-out relative RMSE {e_plain:.4f}")
-
-    model = L.LearnedFBP(N, max(args.batch, H, 16), order=args.order, groups=args.groups,
-                         cnn=True, fit_length=min(N, 512))
-    t1 = time.perf_counter()
-    hist = L.train(model, noisy[tr], target[tr], mask, steps=args.steps, batch=args.batch,
-                   log=log)
-    train_s = time.perf_counter() - t1
-    e_learned = L.relative_rmse(model, noisy[te], target[te], mask)
-    # learned coefficients alone (no network): same cost as the plain method
-    b, a = model.coefficients()
-    coef_only = api.fbp_plan(N, max(S, H), b.detach().numpy(), a.detach().numpy())
-    e_coef = L.relative_rmse(coef_only, noisy[te], target[te], mask)
-    log(f"learned: coefficients only {e_coef:.4f}, with network {e_learned:.4f} "
-        f"(trained {args.steps} steps in {train_s:.1f} s)")
-
-    x = noisy[tr]
-    img = torch.empty((S, N, N), device=dev)
-    t_plain = _timeit(lambda: api.fbp_reconstruct(plain, x, img))
-    t_coef = _timeit(lambda: api.fbp_reconstruct(coef_only, x, img))
-    cnn_w = {k: v.detach() for k, v in model.cnn.items()}
-    with torch.no_grad():
-        t_full = _timeit(lambda: L.residual_cnn(api.fbp_reconstruct(coef_only, x, img), cnn_w))
-    model.save(args.out)
-    out = {
-        "workload": f"{S} noisy slices (I0={args.i0:g}) N={N}, order {args.order} x "
-                    f"{args.groups} angle groups, residual network 1-16-16-1",
-        "rel_rmse_vs_direct_fbp": {"plain": round(e_plain, 5),
-                                   "learned_coefficients": round(e_coef, 5),
-                                   "learned_coefficients_and_network": round(e_learned, 5)},
-        "slices_per_s": {"plain": round(S / t_plain, 1),
-                         "learned_coefficients": round(S / t_coef, 1),
-                         "learned_coefficients_and_network": round(S / t_full, 1)},
-        "fit_rel_err": fit_err, "train_steps": args.steps, "train_seconds": round(train_s, 1),
-        "final_train_loss": hist[-1], "model": args.out,
-    }
-    print(json.dumps(out))
-    plain.close()
-    coef_only.close()
-    model.close()
+    rep = run(args.n, args.slices, args.holdout, args.steps, args.batch, args.i0, args.order,
+              args.groups, args.seed, args.out, log)
+    print(json.dumps(rep))
 
 
 if __name__ == "__main__":

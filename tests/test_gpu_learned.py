@@ -76,6 +76,44 @@ def test_cnn_forward_matches_oracle(gpu_lib):
     assert _rel(got.cpu().double() - x0.double(), ref - x0.double()) < 2e-3
 
 
+def test_cnn_fused_forward_equals_layer_by_layer(gpu_lib):
+    """fbp_cnn_forward (one launch, hidden activations in LDS) against the three fbp_cnn_conv
+    launches: the same matrix-core operations on the same operands, so equal bit for bit,
+    across tile edges (128 x 96 is 8 x 3 tiles of 16 x 32)."""
+    api = gpu_lib
+    import paper_2007_06289_amd.learned as L
+    B, H, W = 2, 128, 96
+    x0 = (I.phantom_image(I.random_ellipses(128, 8, seed=7, batch=B), 128, supersample=2)
+          [:, :, :W].contiguous().to(torch.float32).cuda())
+    w = _cnn_weights(5)
+    p1, p2, p3 = api.fbp_cnn_pack(w["w1"]), api.fbp_cnn_pack(w["w2"]), api.fbp_cnn_pack(w["w3"])
+    fused = api.fbp_cnn_forward(x0, p1, w["b1"], p2, w["b2"], p3, w["b3"])
+    h1 = api.fbp_cnn_conv(1, 16, x0, p1, bias=w["b1"], relu=True)
+    h2 = api.fbp_cnn_conv(16, 16, h1, p2, bias=w["b2"], relu=True)
+    layers = api.fbp_cnn_conv(16, 1, h2, p3, bias=w["b3"], resid=x0)
+    torch.cuda.synchronize()
+    assert torch.equal(fused, layers)
+    with torch.no_grad():
+        assert torch.equal(L.residual_cnn(x0, w), fused)
+
+
+@pytest.mark.parametrize("H,W", [(100, 72), (17, 33), (1, 5)])
+def test_cnn_fused_forward_ragged_sizes_match_oracle(gpu_lib, H, W):
+    """Sizes that are not multiples of the 16 x 32 tile (partial tiles, a single row)."""
+    api = gpu_lib
+    B = 2
+    g = torch.Generator().manual_seed(H * W)
+    x0 = torch.randn(B, H, W, generator=g, dtype=torch.float64).to(torch.float32)
+    w = _cnn_weights(6)
+    got = api.fbp_cnn_forward(x0.cuda(), api.fbp_cnn_pack(w["w1"]), w["b1"],
+                              api.fbp_cnn_pack(w["w2"]), w["b2"], api.fbp_cnn_pack(w["w3"]),
+                              w["b3"])
+    torch.cuda.synchronize()
+    ref = O.residual_cnn(x0.double(), [w["w1"].cpu(), w["w2"].cpu(), w["w3"].cpu()],
+                         [w["b1"].cpu(), w["b2"].cpu(), w["b3"].cpu()], bf16_storage=True)
+    assert _rel(got.cpu().double() - x0.double(), ref - x0.double()) < 2e-3
+
+
 def test_cnn_backward_matches_oracle(gpu_lib):
     import paper_2007_06289_amd.learned as L
     N, B = 64, 2

@@ -16,6 +16,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "fhtfbp_internal.h"
 
 namespace fhtfbp {
@@ -27,10 +29,15 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 __device__ __forceinline__ uint16_t f2bf(float f) {   // round to nearest even (hardware)
   return __builtin_bit_cast(uint16_t, (__bf16)f);
 }
+typedef float float2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+// Two floats as BF16 in one word (a in the low half): one hardware conversion.
+__device__ __forceinline__ uint32_t pack2_bf16(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((float2v){a, b}, bf16x2v));
+}
 // Four channels of one pixel as BF16, packed for one 8-byte store.
 __device__ __forceinline__ uint2 pack4_bf16(float a, float b, float c, float d) {
-  return make_uint2((uint32_t)f2bf(a) | ((uint32_t)f2bf(b) << 16),
-                    (uint32_t)f2bf(c) | ((uint32_t)f2bf(d) << 16));
+  return make_uint2(pack2_bf16(a, b), pack2_bf16(c, d));
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
@@ -211,22 +218,29 @@ __global__ void __launch_bounds__(256) cnn_reduce_kernel(const float* __restrict
 // out = x + conv3(relu(conv2(relu(conv1(x) + b1)) + b2)) + b3 over tiles of TH x TW output
 // pixels.  A block loads the x region the tile depends on (three pixels of halo on each
 // side, zero outside the image) into LDS, computes h1 over the tile plus two pixels of halo
-// and h2 over the tile plus one, both BF16 NHWC in LDS (zero outside the image: the zero
-// padding of the next layer), and writes the tile.  Each layer issues the same matrix-core
-// operations with the same operands as cnn_conv_kernel (same K order, same BF16 roundings,
-// bias then ReLU, then the residual), so the image equals the three separate launches bit for
-// bit; only h1 and h2 never go to HBM.  A group is 16 consecutive pixels of a region in
-// row-major order; lane (m, kg) of a wave ends with channels 4 kg .. + 3 of pixel m.
-constexpr int kFuseTH = 16, kFuseTW = 32;
-constexpr int kXR = kFuseTH + 6, kXC = kFuseTW + 6;      // x region 22 x 38
-constexpr int kH1R = kFuseTH + 4, kH1C = kFuseTW + 4;    // h1 region 20 x 36
-constexpr int kH2R = kFuseTH + 2, kH2C = kFuseTW + 2;    // h2 region 18 x 34
-constexpr int kH1Px = kH1R * kH1C, kH2Px = kH2R * kH2C;
-constexpr int kH1Groups = (kH1Px + 15) / 16, kH2Groups = (kH2Px + 15) / 16;
-// h2 is stored for whole groups of 16 pixels (the last group's extra pixels are never read)
-constexpr int kH2Store = kH2Groups * 16;
-static_assert(kH1Px % 16 == 0, "h1 region in whole groups of 16 pixels");
+// and h2 over the tile plus one, both BF16 in LDS (zero outside the image: the zero padding
+// of the next layer), and writes the tile.  Each layer issues the same matrix-core operations
+// with the same operands as cnn_conv_kernel (same K order, same BF16 roundings, bias then
+// ReLU, then the residual), so the image equals the three separate launches bit for bit;
+// only h1 and h2 never go to HBM.  A group is 16 consecutive pixels of a region in row-major
+// order; lane (m, kg) of a wave ends with channels 4 kg .. + 3 of pixel m.  In LDS the 16
+// channels of a pixel are split in two planes of 8 (16 bytes per pixel and plane): the 16
+// lanes that read one operand half then read 256 consecutive bytes.
+template <int TH, int TW>
+struct FusedTile {
+  static constexpr int XR = TH + 6, XC = TW + 6;         // x region
+  static constexpr int H1R = TH + 4, H1C = TW + 4;       // h1 region
+  static constexpr int H2R = TH + 2, H2C = TW + 2;       // h2 region
+  static constexpr int H1Px = H1R * H1C, H2Px = H2R * H2C;
+  static constexpr int H1Groups = H1Px / 16, H2Groups = (H2Px + 15) / 16;
+  // h2 is stored for whole groups of 16 pixels (the last group's extra pixels are never read)
+  static constexpr int H2Store = H2Groups * 16;
+  static constexpr int OutGroups = TH * (TW / 16);
+  static_assert(H1Px % 16 == 0, "h1 region in whole groups of 16 pixels");
+  static_assert(TW % 16 == 0 && OutGroups % 8 == 0, "output groups pair up");
+};
 
+template <int TH, int TW>
 __global__ void __launch_bounds__(256) cnn_fused_kernel(const float* __restrict__ in,
                                                         const bf16x8* __restrict__ w1,
                                                         const float* __restrict__ b1,
@@ -235,22 +249,17 @@ __global__ void __launch_bounds__(256) cnn_fused_kernel(const float* __restrict_
                                                         const bf16x8* __restrict__ w3,
                                                         const float* __restrict__ b3,
                                                         float* __restrict__ out, int H, int W,
-                                                        int tiles_x, int tiles_per_img) {
-  __shared__ float sx[kXR * kXC];
-  __shared__ __align__(16) uint16_t sh1[kH1Px * 16];
-  __shared__ __align__(16) uint16_t sh2[kH2Store * 16];
+                                                        int tiles_x, int tiles_per_img,
+                                                        int total_tiles) {
+  using T = FusedTile<TH, TW>;
+  constexpr int XPX = T::XR * T::XC;
+  constexpr int XPT = (XPX + 255) / 256;             // x values per thread and tile
+  __shared__ float sx[2][XPX];                       // this tile's x region and the next one's
+  __shared__ __align__(16) uint16_t sh1[2 * T::H1Px * 8];
+  __shared__ __align__(16) uint16_t sh2[2 * T::H2Store * 8];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int m = lane & 15, kg = lane >> 4;
-  const int b = blockIdx.x / tiles_per_img;
-  const int t = blockIdx.x - b * tiles_per_img;
-  const int Y0 = (t / tiles_x) * kFuseTH, X0 = (t % tiles_x) * kFuseTW;
-  const float* img = in + (size_t)b * H * W;
-  for (int e = tid; e < kXR * kXC; e += 256) {
-    const int r = e / kXC, c = e - r * kXC;
-    const int gy = Y0 - 3 + r, gx = X0 - 3 + c;
-    sx[e] = (gy >= 0 && gy < H && gx >= 0 && gx < W) ? img[(size_t)gy * W + gx] : 0.f;
-  }
   const bf16x8 w1op = w1[lane];
   bf16x8 w2op[5], w3op[5];
 #pragma unroll
@@ -265,123 +274,193 @@ __global__ void __launch_bounds__(256) cnn_fused_kernel(const float* __restrict_
     bias2[i] = b2[4 * kg + i];
   }
   const float bias3 = b3[0];
-  __syncthreads();
+  // Operand addressing of layers 2 and 3, fixed per lane: step s reads tap 2 s + kg / 2, i.e.
+  // the pixel (tap / 3) rows and (tap % 3) columns from the lane's base pixel, in channel
+  // plane kg % 2.  Tap 9 (step 4, kg >= 2) does not exist: those lanes read their base pixel
+  // and zero it.
+  int o1[5], o2[5];
+#pragma unroll
+  for (int s = 0; s < 5; ++s) {
+    const int tap = 2 * s + (kg >> 1);
+    o1[s] = tap < 9 ? (tap / 3) * T::H1C + tap % 3 : 0;
+    o2[s] = tap < 9 ? (tap / 3) * T::H2C + tap % 3 : 0;
+  }
+  const bool tap9 = (kg >> 1) != 0;
+  // layer 1's operand words: lane group 0 keeps taps 0..7, group 1 tap 8 (first word)
+  const uint32_t lmask0 = kg == 0 ? 0xffffffffu : 0u, lmask8 = kg == 1 ? 0xffffffffu : 0u;
+  // The weights and biases are waited for here, before the tile loop: an empty asm that reads
+  // them makes the compiler complete their loads once, so that inside the loop no wait for
+  // them also waits for the next tile's x loads, which are issued later.
+  asm volatile("" ::"v"(w1op), "v"(w2op[0]), "v"(w2op[1]), "v"(w2op[2]), "v"(w2op[3]),
+               "v"(w2op[4]));
+  asm volatile("" ::"v"(w3op[0]), "v"(w3op[1]), "v"(w3op[2]), "v"(w3op[3]), "v"(w3op[4]));
+  asm volatile("" ::"v"(bias1[0]), "v"(bias1[1]), "v"(bias1[2]), "v"(bias1[3]), "v"(bias2[0]),
+               "v"(bias2[1]), "v"(bias2[2]), "v"(bias2[3]), "v"(bias3));
+  const uint16_t* sh1l = sh1 + (kg & 1) * T::H1Px * 8;
+  const uint16_t* sh2l = sh2 + (kg & 1) * T::H2Store * 8;
 
-  // Bias, ReLU and BF16 of a lane's four channels of region pixel px (zero outside the image),
-  // stored as one 8-byte word.
-  auto store4 = [&](uint16_t* dst, const f32x4& acc, const float* bias, int px, int cols,
-                    int oy, int ox) {
-    const int rr = px / cols, cc = px - rr * cols;
-    const int gy = Y0 + oy + rr, gx = X0 + ox + cc;
-    const bool inside = gy >= 0 && gy < H && gx >= 0 && gx < W;
-    uint2 w = pack4_bf16(fmaxf(acc[0] + bias[0], 0.f), fmaxf(acc[1] + bias[1], 0.f),
-                         fmaxf(acc[2] + bias[2], 0.f), fmaxf(acc[3] + bias[3], 0.f));
-    if (!inside) w = make_uint2(0u, 0u);
-    *reinterpret_cast<uint2*>(dst + px * 16 + 4 * kg) = w;
+  // The x region of tile tl (three pixels of halo, zero outside the image): loaded into
+  // registers, later stored into one of the two LDS buffers.
+  float xr[XPT];
+  auto load_x = [&](int tl) {
+    const int b = tl / tiles_per_img, t = tl - b * tiles_per_img;
+    const int Y0 = (t / tiles_x) * TH, X0 = (t % tiles_x) * TW;
+    const float* img = in + (size_t)b * H * W;
+#pragma unroll
+    for (int k = 0; k < XPT; ++k) {
+      const int e = tid + k * 256;
+      const int r = e / T::XC, c = e - r * T::XC;
+      const int gy = Y0 - 3 + r, gx = X0 - 3 + c;
+      xr[k] = (e < XPX && gy >= 0 && gy < H && gx >= 0 && gx < W) ? img[(size_t)gy * W + gx]
+                                                                  : 0.f;
+    }
+  };
+  auto store_x = [&](float* dst) {
+#pragma unroll
+    for (int k = 0; k < XPT; ++k)
+      if (tid + k * 256 < XPX) dst[tid + k * 256] = xr[k];
   };
 
-  // layer 1: x (1 channel) -> h1 (16).  Lane group kg holds taps 8 kg .. 8 kg + 7: kg = 0
-  // taps 0..7, kg = 1 tap 8, the rest zero; every lane reads and selects (no branch).
-  for (int g = wave; g < kH1Groups; g += 4) {
-    const int p = g * 16 + m;
-    const int r = p / kH1C, c = p - r * kH1C;
-    const float* xp = sx + r * kXC + c;
-    float v[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const float v0 = xp[(j / 3) * kXC + j % 3];
-      const float v8 = xp[2 * kXC + 2];
-      v[j] = kg == 0 ? v0 : ((kg == 1 && j == 0) ? v8 : 0.f);
-    }
-    bf16x8 a;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) a[j] = (short)f2bf(v[j]);
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1op, a, acc, 0, 0, 0);
-    store4(sh1, acc, bias1, p, kH1C, -2, -2);
-  }
+  int tl = blockIdx.x;
+  if (tl >= total_tiles) return;
+  load_x(tl);
+  store_x(sx[0]);
   __syncthreads();
+  for (int buf = 0; tl < total_tiles; tl += gridDim.x, buf ^= 1) {
+    const int b = tl / tiles_per_img;
+    const int t = tl - b * tiles_per_img;
+    const int Y0 = (t / tiles_x) * TH, X0 = (t % tiles_x) * TW;
+    const float* sxc = sx[buf];
+    // the next tile's x goes out now and lands while this tile's layers run
+    const int tn = tl + (int)gridDim.x;
+    if (tn < total_tiles) load_x(tn);
+    // every region pixel of an interior tile lies in the image: no zeroing to decide
+    const bool interior = Y0 >= 3 && X0 >= 3 && Y0 + TH + 3 <= H && X0 + TW + 3 <= W;
 
-  // The activation operand of step s for the pixel at (r, c) of a 16-channel region of `cols`
-  // columns: K = tap * 16 + channel, lane group kg holds 8 channels of tap 2 s + kg / 2 (zero
-  // past the ninth tap).
-  auto a16 = [&](const uint16_t* src, int cols, int r, int c, int s) -> bf16x8 {
-    const int kk0 = s * 32 + kg * 8;
-    const int tap = kk0 >> 4, c0 = kk0 & 15;
-    bf16x8 a = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
-    if (tap < 9)
-      a = *reinterpret_cast<const bf16x8*>(src + ((r + tap / 3) * cols + c + tap % 3) * 16 + c0);
-    return a;
-  };
+    // Bias, ReLU and BF16 of a lane's four channels of region pixel px (zero outside the
+    // image), stored as one 8-byte word into plane kg / 2 of a region of `px_total` pixels.
+    auto store4 = [&](uint16_t* dst, int px_total, const f32x4& acc, const float* bias, int px,
+                      int cols, int oy, int ox) {
+      uint2 w = pack4_bf16(fmaxf(acc[0] + bias[0], 0.f), fmaxf(acc[1] + bias[1], 0.f),
+                           fmaxf(acc[2] + bias[2], 0.f), fmaxf(acc[3] + bias[3], 0.f));
+      if (!interior) {
+        const int rr = px / cols, cc = px - rr * cols;
+        const int gy = Y0 + oy + rr, gx = X0 + ox + cc;
+        if (!(gy >= 0 && gy < H && gx >= 0 && gx < W)) w = make_uint2(0u, 0u);
+      }
+      *reinterpret_cast<uint2*>(dst + ((kg >> 1) * px_total + px) * 8 + (kg & 1) * 4) = w;
+    };
 
-  // layer 2: h1 (16) -> h2 (16).  A wave takes two groups at a time (its groups g and g + 4;
-  // the second repeats the first when there is none): their operands load together and the
-  // two accumulation chains interleave on the matrix core.
-  for (int g = wave; g < kH2Groups; g += 8) {
-    const int gb = g + 4 < kH2Groups ? g + 4 : g;
-    const int pa = g * 16 + m, pb = gb * 16 + m;           // < kH2Store
-    const int qa = min(pa, kH2Px - 1), qb = min(pb, kH2Px - 1);
-    const int ra = qa / kH2C, ca = qa - ra * kH2C, rb = qb / kH2C, cb = qb - rb * kH2C;
-    bf16x8 aa[5], ab[5];
+    // layer 1: x (1 channel) -> h1 (16).  Lane group kg holds taps 8 kg .. 8 kg + 7: kg = 0
+    // taps 0..7, kg = 1 tap 8, the rest zero; every lane reads and selects (no branch).
+    for (int g = wave; g < T::H1Groups; g += 4) {
+      const int p = g * 16 + m;
+      const int r = p / T::H1C, c = p - r * T::H1C;
+      const float* xp = sxc + r * T::XC + c;
+      // all nine taps are read by every lane (immediate offsets, no branch), converted in
+      // pairs, and each lane keeps its own words: kg = 0 taps 0..7, kg = 1 tap 8, else zero
+      float tv[9];
 #pragma unroll
-    for (int s = 0; s < 5; ++s) {
-      aa[s] = a16(sh1, kH1C, ra, ca, s);
-      ab[s] = a16(sh1, kH1C, rb, cb, s);
-    }
-    f32x4 acca = {0.f, 0.f, 0.f, 0.f}, accb = {0.f, 0.f, 0.f, 0.f};
+      for (int j = 0; j < 9; ++j) tv[j] = xp[(j / 3) * T::XC + j % 3];
+      uint32_t w[4];
 #pragma unroll
-    for (int s = 0; s < 5; ++s) {
-      acca = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2op[s], aa[s], acca, 0, 0, 0);
-      accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2op[s], ab[s], accb, 0, 0, 0);
+      for (int k = 0; k < 4; ++k) w[k] = pack2_bf16(tv[2 * k], tv[2 * k + 1]) & lmask0;
+      w[0] |= pack2_bf16(tv[8], 0.f) & lmask8;
+      const bf16x8 a = __builtin_bit_cast(bf16x8, make_uint4(w[0], w[1], w[2], w[3]));
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1op, a, acc, 0, 0, 0);
+      store4(sh1, T::H1Px, acc, bias1, p, T::H1C, -2, -2);
     }
-    store4(sh2, acca, bias2, pa, kH2C, -1, -1);
-    store4(sh2, accb, bias2, pb, kH2C, -1, -1);
-  }
-  __syncthreads();
+    __syncthreads();   // h1 complete; the previous tile's layer 3 is done with h2
 
-  // layer 3: h2 (16) -> 1 channel (channel 0: lanes kg = 0, first element), plus bias and the
-  // residual; a group is 16 pixels of a tile row, two groups (g, g + 4) per wave at a time
-  float* dst = out + (size_t)b * H * W;
-  constexpr int kOutGroups = kFuseTH * (kFuseTW / 16);
-  static_assert(kOutGroups % 8 == 0, "output groups pair up");
-  for (int g = wave; g < kOutGroups; g += 8) {
-    bf16x8 aa[5], ab[5];
-    const int ra = g / (kFuseTW / 16), ca = (g % (kFuseTW / 16)) * 16 + m;
-    const int rb = (g + 4) / (kFuseTW / 16), cb = ((g + 4) % (kFuseTW / 16)) * 16 + m;
+    // The activation operand of step s for base pixel index q of a 16-channel region (lane
+    // plane `src`, per-lane tap offsets `o`): K = tap * 16 + channel; zero past the ninth tap.
+    auto a16 = [&](const uint16_t* src, const int* o, int q, int s) -> bf16x8 {
+      bf16x8 a = *reinterpret_cast<const bf16x8*>(src + (q + o[s]) * 8);
+      if (s == 4 && tap9) a = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+      return a;
+    };
+
+    // layer 2: h1 (16) -> h2 (16).  A wave takes two groups at a time (its groups g and g + 4;
+    // the second repeats the first when there is none): their operands load together and the
+    // two accumulation chains interleave on the matrix core.
+    for (int g = wave; g < T::H2Groups; g += 8) {
+      const int gb = g + 4 < T::H2Groups ? g + 4 : g;
+      const int pa = g * 16 + m, pb = gb * 16 + m;           // < H2Store
+      const int qa = min(pa, T::H2Px - 1), qb = min(pb, T::H2Px - 1);
+      const int ra = qa / T::H2C, ca = qa - ra * T::H2C, rb = qb / T::H2C, cb = qb - rb * T::H2C;
+      const int ba = ra * T::H1C + ca, bb = rb * T::H1C + cb;   // base pixels in the h1 region
+      bf16x8 aa[5], ab[5];
 #pragma unroll
-    for (int s = 0; s < 5; ++s) {
-      aa[s] = a16(sh2, kH2C, ra, ca, s);
-      ab[s] = a16(sh2, kH2C, rb, cb, s);
-    }
-    f32x4 acca = {0.f, 0.f, 0.f, 0.f}, accb = {0.f, 0.f, 0.f, 0.f};
+      for (int s = 0; s < 5; ++s) {
+        aa[s] = a16(sh1l, o1, ba, s);
+        ab[s] = a16(sh1l, o1, bb, s);
+      }
+      f32x4 acca = {0.f, 0.f, 0.f, 0.f}, accb = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int s = 0; s < 5; ++s) {
-      acca = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3op[s], aa[s], acca, 0, 0, 0);
-      accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3op[s], ab[s], accb, 0, 0, 0);
+      for (int s = 0; s < 5; ++s) {
+        acca = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2op[s], aa[s], acca, 0, 0, 0);
+        accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2op[s], ab[s], accb, 0, 0, 0);
+      }
+      store4(sh2, T::H2Store, acca, bias2, pa, T::H2C, -1, -1);
+      store4(sh2, T::H2Store, accb, bias2, pb, T::H2C, -1, -1);
     }
-    if (kg == 0) {
-      const int gya = Y0 + ra, gxa = X0 + ca, gyb = Y0 + rb, gxb = X0 + cb;
-      if (gya < H && gxa < W)
-        dst[(size_t)gya * W + gxa] = acca[0] + bias3 + sx[(ra + 3) * kXC + ca + 3];
-      if (gyb < H && gxb < W)
-        dst[(size_t)gyb * W + gxb] = accb[0] + bias3 + sx[(rb + 3) * kXC + cb + 3];
+    if (tn < total_tiles) store_x(sx[buf ^ 1]);
+    __syncthreads();   // h2 and the next tile's x region complete
+
+    // layer 3: h2 (16) -> 1 channel (channel 0: lanes kg = 0, first element), plus bias and
+    // the residual; a group is 16 pixels of a tile row, two groups (g, g + 4) per wave at a time
+    float* dst = out + (size_t)b * H * W;
+    for (int g = wave; g < T::OutGroups; g += 8) {
+      bf16x8 aa[5], ab[5];
+      const int ra = g / (TW / 16), ca = (g % (TW / 16)) * 16 + m;
+      const int rb = (g + 4) / (TW / 16), cb = ((g + 4) % (TW / 16)) * 16 + m;
+#pragma unroll
+      for (int s = 0; s < 5; ++s) {
+        aa[s] = a16(sh2l, o2, ra * T::H2C + ca, s);
+        ab[s] = a16(sh2l, o2, rb * T::H2C + cb, s);
+      }
+      f32x4 acca = {0.f, 0.f, 0.f, 0.f}, accb = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < 5; ++s) {
+        acca = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3op[s], aa[s], acca, 0, 0, 0);
+        accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3op[s], ab[s], accb, 0, 0, 0);
+      }
+      if (kg == 0) {
+        const int gya = Y0 + ra, gxa = X0 + ca, gyb = Y0 + rb, gxb = X0 + cb;
+        if (gya < H && gxa < W)
+          dst[(size_t)gya * W + gxa] = acca[0] + bias3 + sxc[(ra + 3) * T::XC + ca + 3];
+        if (gyb < H && gxb < W)
+          dst[(size_t)gyb * W + gxb] = accb[0] + bias3 + sxc[(rb + 3) * T::XC + cb + 3];
+      }
     }
   }
 }
 
 }  // namespace
 
+// Output tile of the fused network: 16 x 32 pixels (50 KB of LDS per block).  The launch is
+// persistent: as many blocks as the device holds at once, each looping over tiles.
+constexpr int kFuseTH = 16, kFuseTW = 32;
+
 hipError_t launch_cnn_fused(const float* in, const uint16_t* w1, const float* b1,
                             const uint16_t* w2, const float* b2, const uint16_t* w3,
                             const float* b3, float* out, int batch, int H, int W,
                             hipStream_t stream) {
   const int tiles_x = (W + kFuseTW - 1) / kFuseTW, tiles_y = (H + kFuseTH - 1) / kFuseTH;
-  const long long blocks = (long long)batch * tiles_x * tiles_y;
-  if (blocks > 0x7fffffffll) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(cnn_fused_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, in,
+  const long long tiles = (long long)batch * tiles_x * tiles_y;
+  if (tiles > 0x7fffffffll) return hipErrorInvalidValue;
+  auto kern = cnn_fused_kernel<kFuseTH, kFuseTW>;
+  int dev = 0, cus = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0);
+  if (e != hipSuccess) return e;
+  const long long grid = std::min<long long>(tiles, (long long)cus * std::max(per_cu, 1));
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), 0, stream, in,
                      reinterpret_cast<const bf16x8*>(w1), b1, reinterpret_cast<const bf16x8*>(w2),
                      b2, reinterpret_cast<const bf16x8*>(w3), b3, out, H, W, tiles_x,
-                     tiles_x * tiles_y);
+                     tiles_x * tiles_y, (int)tiles);
   return hipGetLastError();
 }
 

@@ -353,12 +353,11 @@ __global__ void __launch_bounds__(256) cnn_fused_kernel(const float* __restrict_
 
     // layer 1: x (1 channel) -> h1 (16).  Lane group kg holds taps 8 kg .. 8 kg + 7: kg = 0
     // taps 0..7, kg = 1 tap 8, the rest zero; every lane reads and selects (no branch).
-    for (int g = wave; g < T::H1Groups; g += 4) {
-      const int p = g * 16 + m;
+    // all nine taps are read by every lane (immediate offsets, no branch), converted in pairs,
+    // and each lane keeps its own words: kg = 0 taps 0..7, kg = 1 tap 8, else zero
+    auto a1 = [&](int p) -> bf16x8 {
       const int r = p / T::H1C, c = p - r * T::H1C;
       const float* xp = sxc + r * T::XC + c;
-      // all nine taps are read by every lane (immediate offsets, no branch), converted in
-      // pairs, and each lane keeps its own words: kg = 0 taps 0..7, kg = 1 tap 8, else zero
       float tv[9];
 #pragma unroll
       for (int j = 0; j < 9; ++j) tv[j] = xp[(j / 3) * T::XC + j % 3];
@@ -366,10 +365,18 @@ __global__ void __launch_bounds__(256) cnn_fused_kernel(const float* __restrict_
 #pragma unroll
       for (int k = 0; k < 4; ++k) w[k] = pack2_bf16(tv[2 * k], tv[2 * k + 1]) & lmask0;
       w[0] |= pack2_bf16(tv[8], 0.f) & lmask8;
-      const bf16x8 a = __builtin_bit_cast(bf16x8, make_uint4(w[0], w[1], w[2], w[3]));
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1op, a, acc, 0, 0, 0);
-      store4(sh1, T::H1Px, acc, bias1, p, T::H1C, -2, -2);
+      return __builtin_bit_cast(bf16x8, make_uint4(w[0], w[1], w[2], w[3]));
+    };
+    // two groups (g, g + 4) at a time, as in the layers below
+    for (int g = wave; g < T::H1Groups; g += 8) {
+      const int gb = g + 4 < T::H1Groups ? g + 4 : g;
+      const int pa = g * 16 + m, pb = gb * 16 + m;
+      const bf16x8 aa = a1(pa), ab = a1(pb);
+      f32x4 acca = {0.f, 0.f, 0.f, 0.f}, accb = {0.f, 0.f, 0.f, 0.f};
+      acca = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1op, aa, acca, 0, 0, 0);
+      accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1op, ab, accb, 0, 0, 0);
+      store4(sh1, T::H1Px, acca, bias1, pa, T::H1C, -2, -2);
+      store4(sh1, T::H1Px, accb, bias1, pb, T::H1C, -2, -2);
     }
     __syncthreads();   // h1 complete; the previous tile's layer 3 is done with h2
 

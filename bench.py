@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--cpu-slices", type=int, default=96)
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-filter leg (128 + 16 noisy slices of N = 1024)")
+    ap.add_argument("--only-learned", action="store_true",
+                    help="run only the learned-filter leg and print its JSON (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (for scaling the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -360,6 +362,11 @@ def main():
     import paper_2007_06289_amd as F
 
     N, B = args.n, args.batch
+    if args.only_learned:
+        torch.cuda.init()
+        F.load_library()
+        print(json.dumps({"learned": learned_leg(N)}))
+        return
     dev = "cuda"
     torch.cuda.init()
     F.load_library()

@@ -53,6 +53,22 @@ def test_direct_linogram_fbp_matches_oracle(gpu_lib, N):
     assert _rel(got, ref) < 1e-4
 
 
+@pytest.mark.parametrize("N", [64, 256])
+def test_exact_ramp_rows_through_hough_backprojection_match_oracle(gpu_lib, N):
+    """The back-projection sweep's Hough arm: the direct FBP's exact-ramp rows (window order)
+    put back at their cyclic shifts and back-projected by the FHT equal the oracle's FHT-FBP
+    with the exact ramp as its filter (b = h+ over the whole row, no feedback, eq 10-12)."""
+    api = gpu_lib
+    from paper_2007_06289_amd import sweeps
+    P = I.linogram(I.random_ellipses(N, 10, seed=N + 1, batch=2), N).to(torch.float32)
+    work = torch.empty((2, 4 * N, N), device="cuda")
+    api.fbp_direct_linogram(P.cuda(), work=work)
+    got = sweeps._hough_backprojection(work.view(2, 4, N, N), N)
+    torch.cuda.synchronize()
+    ref = O.fbp_fht(P.double(), O.ramp_causal(N), torch.zeros(1, dtype=torch.float64))
+    assert _rel(got, ref) < 1e-5
+
+
 def _cnn_weights(seed):
     import paper_2007_06289_amd.learned as L
     w = L.init_cnn(seed, scale=0.2)

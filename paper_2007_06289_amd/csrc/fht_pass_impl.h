@@ -2139,6 +2139,199 @@ fht_image_tile_kernel(PassArgs A) {
     for (int k = 0; k < 4; ++k) img[(size_t)(r + 16 * m) * N + c + 32 * k] = acc[m][k];
 }
 
+// ---- last pass of 7 levels over square image tiles ----------------------------------------------
+// The same image tile as above (128 x 128, all four classes, the image written once), for a last
+// pass of 7 levels: each class reaches the tile through one strip of 128 rows (the tile's rows
+// for classes 0 and 1, its columns for classes 2 and 3) by 128 + 128 columns (the halo below).
+// A strip fills the LDS, so the block runs the classes one after the other: level 0 in
+// registers at the deposit, levels 1 .. 6 as three radix-4 stages, then the strip is added
+// into accumulators held in registers (class 0, + class 1, then + class 2, + class 3: the
+// additions, and their order, of the other last-pass kernels, so results are bit-identical).
+// The next strip's loads are in flight while the current one runs its levels.
+//
+// LDS layout: one class, rows of kT7Rs floats after a margin of kT7Margin floats (row i at
+// kT7Margin + i kT7Rs).  Columns 0 .. 255 hold the strip; the stages compute 5 blocks of 61
+// columns (-3 .. 301) with no clamping: reads below column 0 land in the margin or the row
+// before's padding, writes of columns -3 .. -1 in the row before's padding, columns above 255
+// are garbage, and none of these feed columns 128 .. 255, the only ones read out (an output
+// column depends only on the 127 columns below it).
+constexpr int kT7Rows = 128, kT7Cols = 256;
+constexpr int kT7Rs = 308;       // > 304 + 3: rows written over -3 .. 304 never overlap
+constexpr int kT7Margin = 128;   // >= 100: the lowest read is column -3 - 31 - 63 of row 0
+constexpr int kT7LdsFloats = kT7Margin + kT7Rows * kT7Rs;
+static_assert(kT7LdsFloats * 4 <= kLdsBudget, "a 128-row strip fits the LDS");
+static_assert((kT7Rs % 4) == 0 && (kT7Margin % 4) == 0, "16-byte aligned rows");
+
+// Levels (l, l + 1) of a 128-row strip (l = 1, 3, 5): 32 units of four rows, two per wave (16
+// waves), 5 blocks of 61 columns each; the radix-4 form of tile_stage4.  A unit's rows belong to
+// no other unit of the stage, so a wave reads all blocks of one unit, writes them, then takes
+// its next unit, with no barrier in between.  (Reads at negative columns reach into the row
+// before, which another wave may be rewriting; they only feed columns below 128 - 127 + ...,
+// i.e. columns that no output reads, as everything below column 0 does.)
+__device__ __forceinline__ void tile7_stage4(float* S, int l) {
+  constexpr int UPW = 2, NB = 5, rs = kT7Rs;
+  const int lane = threadIdx.x & 63, wave = wave_id(), waves = blockDim.x >> 6;
+#pragma unroll
+  for (int k = 0; k < UPW; ++k) {
+    const int u = wave + k * waves;                  // 32 units of four rows
+    const int pp = u >> l, ib = u & ((1 << l) - 1);
+    const int rb = (pp << (l + 2)) + ib;
+    const int J = brev_bits(ib, l);
+    const int J2 = brev_bits(ib, l + 1);
+    float* p0 = S + rb * rs + lane - 3;
+    const float* p1 = p0 + (rs << l) - J;
+    const float* p2 = p0 + (rs << (l + 1)) - J2;
+    const float* p3 = p2 + (rs << l) - J;
+    float o0[NB], o1[NB], o2[NB], o3[NB];
+#pragma unroll
+    for (int blk = 0; blk < NB; ++blk) {
+      const float a = p0[61 * blk];
+      const float b = p1[61 * blk];
+      const float f = p2[61 * blk];
+      const float g = p3[61 * blk];
+      const float A0 = a + b;
+      const float A1 = a + lanes_shift_up_any(b);
+      const float A2e = f + g;
+      const float A3e = f + lanes_shift_up_any(g);
+      const float t = lanes_shift_up_any(A3e);
+      o0[blk] = A0 + A2e;
+      o2[blk] = A0 + lanes_shift_up_any(A2e);
+      o1[blk] = A1 + t;
+      o3[blk] = A1 + lanes_shift_up_any(t);
+    }
+    // every read of the unit is done (its values are in registers) before its first write
+    asm volatile("" ::: "memory");
+    auto put = [&](int blk) {
+      p0[61 * blk] = o0[blk];
+      p0[(rs << l) + 61 * blk] = o1[blk];
+      p0[(rs << (l + 1)) + 61 * blk] = o2[blk];
+      p0[(rs << (l + 1)) + (rs << l) + 61 * blk] = o3[blk];
+    };
+    // as in tile_stage4: lanes 0 .. 2 of the blocks above the first are left out (they repeat
+    // the previous block's top columns without their shifted inputs)
+    if (lane >= 3) {
+#pragma unroll
+      for (int blk = 1; blk < NB; ++blk) put(blk);
+    }
+    put(0);
+  }
+  __syncthreads();
+}
+
+// One 128-row strip in registers: thread t takes row pair m = t >> 4 and the float4 columns
+// 4 (j + 16 i), j = t & 15, i < 4, of both rows (256 columns from `col` - 128, cyclically).
+struct Strip7Regs {
+  u32x4 a[4], b[4];
+};
+
+__device__ __forceinline__ void strip7_issue(Strip7Regs& P, const float* cls, int col, int row0,
+                                             int log2n) {
+  const int N = 1 << log2n, mask = N - 1;
+  const int tid = threadIdx.x, m = tid >> 4, j = tid & 15;
+  const __amdgpu_buffer_rsrc_t rsrc =
+      __builtin_amdgcn_make_buffer_rsrc((void*)cls, (short)0, N * N * 4, kBufferDword3);
+  const int rowb = (row0 + 2 * m) * N;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int o = (rowb + ((col - 128 + 4 * (j + 16 * i)) & mask)) * 4;
+    P.a[i] = __builtin_amdgcn_raw_buffer_load_b128(rsrc, o, 0, 0);
+    P.b[i] = __builtin_amdgcn_raw_buffer_load_b128(rsrc, o + N * 4, 0, 0);
+  }
+}
+
+// Level 0 on the strip's registers (lower = r0[x] + r1[x], upper = r0[x] + r1[x - 1]) and the
+// deposit.  r1[x - 1] at the first column of a float4 is the last value of the float4 before
+// (the lane below, or lane 15 of the previous i); strip column 0 has none and is not needed.
+__device__ __forceinline__ void strip7_deposit(const Strip7Regs& P, float* S) {
+  const int tid = threadIdx.x, m = tid >> 4, j = tid & 15;
+  float* lo = S + kT7Margin + (2 * m) * kT7Rs;
+  float* up = lo + kT7Rs;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float a0 = __uint_as_float(P.a[i].x), a1 = __uint_as_float(P.a[i].y);
+    const float a2 = __uint_as_float(P.a[i].z), a3 = __uint_as_float(P.a[i].w);
+    const float b0 = __uint_as_float(P.b[i].x), b1 = __uint_as_float(P.b[i].y);
+    const float b2 = __uint_as_float(P.b[i].z), b3 = __uint_as_float(P.b[i].w);
+    const float below = __shfl_up(b3, 1, 16);                       // float4 j - 1, same i
+    const float wrap = i > 0 ? __shfl(__uint_as_float(P.b[i - 1].w), 15, 16) : 0.f;
+    const float prev = j == 0 ? wrap : below;
+    const int x = 4 * (j + 16 * i);
+    float4* lo4 = reinterpret_cast<float4*>(__builtin_assume_aligned(lo + x, 16));
+    float4* up4 = reinterpret_cast<float4*>(__builtin_assume_aligned(up + x, 16));
+    *lo4 = make_float4(a0 + b0, a1 + b1, a2 + b2, a3 + b3);
+    *up4 = make_float4(a0 + prev, a1 + b0, a2 + b1, a3 + b2);
+  }
+}
+
+// Thread t owns rows (t >> 5) + 32 m and columns (t & 31) + 32 k (m, k < 4) of the tile.
+__global__ void __launch_bounds__(1024) fht_image_tile7_kernel(PassArgs A) {
+  extern __shared__ float S[];
+  constexpr int F = 7, TT = 128, W = 128, H = 128, rs = kT7Rs;
+  const int tid = threadIdx.x;
+  const int N = 1 << A.log2n;
+  const int tpr = N / TT;
+  const int per_slice = tpr * tpr;
+  // consecutive tiles of a row go to one XCD, whose L2 then serves the halo columns they share
+  int id = blockIdx.x;
+  if ((gridDim.x & 7) == 0) id = (id & 7) * (gridDim.x >> 3) + (id >> 3);
+  const int b = id / per_slice, rest = id - b * per_slice;
+  const int ty = rest / tpr, tx = rest - ty * tpr;
+  const int y0 = ty * TT, x0 = tx * TT;
+  const size_t nn = (size_t)N * N;
+  const float* lino = A.in + (size_t)b * 4 * nn;
+  const int c = tid & 31, r = tid >> 5;
+  float acc[4][4];
+  const float* T0 = S + kT7Margin;
+  // class q's strip: rows (q < 2 ? y0 : x0) .. + 127, column block at (q even ? x0 or y0 : the
+  // mirrored block)
+  auto issue = [&](Strip7Regs& P, int q) {
+    const int blk = q < 2 ? x0 : y0;
+    const int col = (q & 1) ? N - blk - W : blk;
+    strip7_issue(P, lino + q * nn, col, q < 2 ? y0 : x0, A.log2n);
+  };
+  Strip7Regs P;
+  issue(P, 0);
+  for (int q = 0; q < 4; ++q) {
+    strip7_deposit(P, S);
+    __syncthreads();
+    if (q + 1 < 4) issue(P, q + 1);
+    tile7_stage4(S + kT7Margin, 1);
+    tile7_stage4(S + kT7Margin, 3);
+    tile7_stage4(S + kT7Margin, 5);
+    if (q < 2) {
+      // image row i = r + 32 m is strip row brev(i); column x = c + 32 k is strip column
+      // H + x (class 0) or H + W - 1 - x (class 1)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const float* row = T0 + brev_bits(r + 32 * m, F) * rs;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          if (q == 0) acc[m][k] = row[H + c + 32 * k];
+          else acc[m][k] = acc[m][k] + row[H + W - 1 - c - 32 * k];
+        }
+      }
+    } else {
+      // image column x = c + 32 k is strip row brev(x); row y = r + 32 m is strip column H + y
+      // (class 2) or H + W - 1 - y (class 3)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float* row = T0 + brev_bits(c + 32 * k, F) * rs;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          if (q == 2) acc[m][k] = acc[m][k] + row[H + r + 32 * m];
+          else acc[m][k] = acc[m][k] + row[H + W - 1 - r - 32 * m];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  float* img = A.out + (size_t)b * nn + (size_t)y0 * N + x0;
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) img[(size_t)(r + 32 * m) * N + c + 32 * k] = acc[m][k];
+}
+
 template <typename Kern>
 hipError_t launch_kernel(Kern kern, const PassArgs& a, int blocks, int threads, size_t lds,
                          hipStream_t stream) {

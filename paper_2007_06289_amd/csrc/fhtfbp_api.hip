@@ -363,6 +363,8 @@ int check_schedule(const fbp_plan_s* p, const std::vector<int>& lv, int log2w) {
     t.log2w = log2w;
     t.halo = std::max(4, 1 << F);
     t.out_mode = (i + 1 == lv.size()) ? OUT_IMG_V : OUT_ROWS;
+    // a last pass of 5 or 7 levels runs over square image tiles, whatever the width
+    if (i + 1 == lv.size() && (F == 5 || F == 7)) continue;
     if (cols_lds_bytes(t) > (size_t)kLdsBudget) return FBP_ERANGE;
   }
   return FBP_OK;
@@ -475,7 +477,7 @@ int run_passes(fbp_plan_s* p, const float* in, float* out, int batch, bool forwa
     } else {
       A.out = out;
       A.out_mode = OUT_IMG_V;
-      if (cols && F == 5) {
+      if (cols && (F == 5 || F == 7)) {
         // all four classes over square image tiles: the image is written once
         e = timed_pass(p, A, batch, FBP_KERNEL_LAST, is, PASS_IMAGE);
       } else {

@@ -37,12 +37,15 @@ def _rel(got, ref):
 
 @pytest.mark.parametrize("N,B,order,schedules", [
     (64, 2, 2, [[6], [3, 3], [2, 2, 2], [1, 5], [5, 1]]),
-    (256, 2, 2, [[4, 4, 0], [2, 6, 7], [4, 4, 7], [4, 4, 6], [3, 3, 2, 8], [1, 1, 6, 7]]),
-    (1024, 2, 2, [[5, 5, 7], [5, 5, 9], [4, 6, 7], [3, 3, 4, 8], [2, 4, 4, 8], [5, 1, 4, 8]]),
-    (1024, 1, 4, [[4, 6, 7], [3, 3, 4, 8], [5, 1, 4, 8]]),
-    (2048, 1, 2, [[4, 4, 3, 8], [3, 5, 3, 8], [4, 3, 4, 9], [2, 3, 3, 3, 8]]),
-    (4096, 1, 2, [[3, 4, 5, 8], [1, 6, 5, 8], [3, 5, 4, 8], [2, 5, 5, 9]]),
-    (4096, 1, 4, [[3, 4, 5, 8], [1, 6, 5, 8], [3, 5, 4, 8]]),
+    (256, 2, 2, [[4, 4, 0], [2, 6, 7], [4, 4, 7], [4, 4, 6], [3, 3, 2, 8], [1, 1, 6, 7],
+                 [1, 7, 8]]),
+    (512, 2, 2, [[2, 7, 8], [1, 1, 7, 8]]),
+    (1024, 2, 2, [[5, 5, 7], [5, 5, 9], [4, 6, 7], [3, 3, 4, 8], [2, 4, 4, 8], [5, 1, 4, 8],
+                  [3, 7, 8], [1, 2, 7, 8]]),
+    (1024, 1, 4, [[4, 6, 7], [3, 3, 4, 8], [5, 1, 4, 8], [3, 7, 8]]),
+    (2048, 1, 2, [[4, 4, 3, 8], [3, 5, 3, 8], [4, 3, 4, 9], [2, 3, 3, 3, 8], [4, 7, 8]]),
+    (4096, 1, 2, [[3, 4, 5, 8], [1, 6, 5, 8], [3, 5, 4, 8], [2, 5, 5, 9], [3, 2, 7, 8]]),
+    (4096, 1, 4, [[3, 4, 5, 8], [1, 6, 5, 8], [3, 5, 4, 8], [3, 2, 7, 8]]),
 ])
 def test_schedules_are_bit_identical(gpu_lib, N, B, order, schedules):
     """Every listed schedule is one the kernels can run (last entry: log2 of the column-tile

@@ -144,9 +144,16 @@ int fbp_filter_coef_grad(fbp_plan_t plan, const float* lino, const float* grad_o
 /* Host-side fit of the recursive ramp pair (Sec. 3): minimise the squared error between the
  * impulse response of eq 9 and the causal half h+ of eq 10 over n = 0..length-1 by the
  * Nelder-Mead simplex method (a parameterised through reflection coefficients, so the fit is
- * always stable; b by linear least squares for each a).  flags bit 0: constrain
- * sum(b) = 0 (zero response at zero frequency, as the ramp has).  Writes b[order],
- * a[order] and the relative L2 error of the fit.  Deterministic.  No GPU needed. */
+ * always stable; b by linear least squares for each a).  flags bit 0 (FBP_FIT_DC_ZERO):
+ * constrain sum(b) = 0 (zero response at zero frequency, as the ramp has).  flags bit 1
+ * (FBP_FIT_FREQUENCY, not in the paper): fit the pair's frequency response
+ * 2 Re(B(e^{iw}) / A(e^{iw})) to the ramp's |w| / (2 pi) in relative squared error at 256
+ * frequencies spaced evenly in log w over [pi / length, pi] (the low frequencies the
+ * time-domain criterion barely weighs).  Writes b[order], a[order] and the relative error of
+ * the fit (L2 over the impulse response; RMS over the frequency grid with bit 1).
+ * Deterministic.  No GPU needed. */
+#define FBP_FIT_DC_ZERO    1u
+#define FBP_FIT_FREQUENCY  2u
 int fbp_fit_ramp_iir(int32_t order, int32_t length, uint32_t flags, double* b, double* a,
                      double* rel_err);
 

@@ -35,6 +35,7 @@ FBP_NO_SCRATCH = 8
 FBP_NOALLOC_SCRATCH_BYTES = 256 << 20
 
 FIT_DC_ZERO = 1
+FIT_FREQUENCY = 2
 
 _lib = None
 
@@ -339,13 +340,16 @@ def fbp_filter_coef_grad(plan: Plan, lino: torch.Tensor, grad_out: torch.Tensor)
     return out
 
 
-def fbp_fit_ramp_iir(order: int, length: int, dc_zero: bool = True):
-    """Fit the recursive ramp pair on the host; returns (b, a, relative L2 error)."""
+def fbp_fit_ramp_iir(order: int, length: int, dc_zero: bool = True, frequency: bool = False):
+    """Fit the recursive ramp pair on the host; returns (b, a, relative error of the fit).
+    ``frequency``: fit the frequency response to the ramp in relative error (not the paper's
+    time-domain criterion; see fbp_fit_ramp_iir in include/fhtfbp.h)."""
     b = np.zeros(order, dtype=np.float64)
     a = np.zeros(order, dtype=np.float64)
     err = ctypes.c_double()
     dp = ctypes.POINTER(ctypes.c_double)
-    _check(load_library().fbp_fit_ramp_iir(int(order), int(length), FIT_DC_ZERO if dc_zero else 0,
+    flags = (FIT_DC_ZERO if dc_zero else 0) | (FIT_FREQUENCY if frequency else 0)
+    _check(load_library().fbp_fit_ramp_iir(int(order), int(length), flags,
                                            b.ctypes.data_as(dp), a.ctypes.data_as(dp),
                                            ctypes.byref(err)), "fbp_fit_ramp_iir")
     return b, a, float(err.value)

@@ -88,6 +88,41 @@ def test_host_fit_matches_the_ramp_half(order, dc0, bound):
     assert np.abs(np.roots(np.concatenate([[1.0], a]))).max() < 1.0
 
 
+@pytest.mark.parametrize("order", [3, 4])
+def test_host_frequency_fit_matches_the_ramp_response(order):
+    """The optional frequency-domain fit: the pair's response 2 Re(B/A) checked independently
+    with scipy.signal.freqz against the ramp's |w| / (2 pi) (the band-limited ramp of eq 7 at
+    unit spacing) at the fit's own frequencies, poles within 1 - 2 / length, sum(b) = 0."""
+    import scipy.signal
+    from paper_2007_06289_amd import api
+    L = 128
+    b, a, err = api.fbp_fit_ramp_iir(order, L, dc_zero=True, frequency=True)
+    w = np.exp(np.linspace(np.log(np.pi / L), np.log(np.pi), 256))
+    _, H = scipy.signal.freqz(b, np.concatenate([[1.0], a]), worN=w)
+    rel = 2 * H.real / (w / (2 * np.pi)) - 1
+    assert abs(float(np.sqrt(np.mean(rel ** 2))) - err) < 1e-9
+    assert err < {3: 0.08, 4: 0.02}[order]
+    assert abs(b.sum()) < 1e-12
+    assert np.abs(np.roots(np.concatenate([[1.0], a]))).max() < 1 - 2 / L + 1e-9
+
+
+def test_frequency_fit_reconstructs_closer_to_the_direct_fbp():
+    """Reported accuracy, not a pin of the paper: at N = 128 the order-4 pair fitted in the
+    frequency domain brings the oracle's FHT-FBP within 0.08 of the oracle's direct FBP, where
+    the paper's time-domain fit of the same order stays above 0.3 (its low-frequency error)."""
+    import fbp_inputs as I
+    from paper_2007_06289_amd import api
+    N = 128
+    P = I.linogram(I.random_ellipses(N, 30, seed=5, batch=1), N)
+    ref = O.fbp_direct_linogram(P)
+    mask = I.support_mask(N)
+    errs = {}
+    for freq in (False, True):
+        b, a, _ = api.fbp_fit_ramp_iir(4, N, dc_zero=True, frequency=freq)
+        errs[freq] = O.relative_rmse(O.fbp_fht(P, torch.tensor(b), torch.tensor(a)), ref, mask)
+    assert errs[True] < 0.08 < 0.3 < errs[False]
+
+
 def test_schedule_and_graph_entry_points_reject_bad_arguments(lib):
     assert lib.fbp_plan_set_schedule(None, None, 0, 0) == -1
     assert lib.fbp_plan_schedule_info(None, None, None) == -1

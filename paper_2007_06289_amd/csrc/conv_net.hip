@@ -1,18 +1,28 @@
 // Learned residual correction applied after the reconstruction: 3x3 convolutions (zero
 // padding 1) with 1 or 16 channels, as implicit GEMMs on the matrix cores (BF16 operands, FP32
-// accumulation, v_mfma_f32_16x16x32_bf16), plus FP32 weight gradients.
+// accumulation), plus FP32 weight gradients.
 //
 // Activations with 16 channels are stored BF16, NHWC ([b][y][x][c], 32 bytes per pixel);
 // single-channel images are FP32 [b][y][x].  A wave computes 16 consecutive pixels of one row
-// x 16 output channels: out[p][n] = sum_kk Act[p][kk] Wg[kk][n], kk = tap * CIN + ci (tap =
-// 3 (dy + 1) + dx + 1), in steps of 32 kk.  Operand layouts of the 16x16x32 instruction: lane l
-// holds A[l % 16][8 (l / 16) .. + 7] and B[8 (l / 16) .. + 7][l % 16]; the result C[4 (l / 16) +
-// i][l % 16] for i < 4.  The weights go in as A (Wg transposed: A[n][kk]) and the activations as
-// B (B[kk][p]), so the instruction yields out transposed: lane l holds channels 4 (l / 16) ..
-// + 3 of pixel l % 16, which it stores as one 8-byte word.  BF16 rounding is the hardware's
-// round-to-nearest-even conversion.  The backward convolution with respect to the input is the
-// same kernel with the weights transposed and the taps flipped (packed by cnn_pack_kernel), and
-// its output multiplied by the ReLU mask of the layer below.
+// x 16 output channels: out[p][n] = sum_kk Act[p][kk] Wg[kk][n].  The weights go in as the A
+// operand (Wg transposed: A[n][kk]) and the activations as B (B[kk][p]), so the instruction
+// yields out transposed: lane l holds channels 4 (l / 16) .. + 3 of pixel l % 16 (C[4 (l / 16) +
+// i][l % 16], i < 4), which it stores as one 8-byte word.  Operand layouts: in a 16x16x32 step
+// lane l holds A[l % 16][8 (l / 16) .. + 7] and B[8 (l / 16) .. + 7][l % 16]; in a 16x16x16 step
+// A[l % 16][4 (l / 16) .. + 3] and B[4 (l / 16) .. + 3][l % 16].
+//
+// K order (taps t = 3 dy + dx, dy, dx in 0..2 for the offsets -1..1), chosen so that each lane's
+// reads are one base per step kind plus immediate offsets, with no padding taps:
+//   16 input channels: four 16x16x32 steps s = 0..3, lane group g = l / 16 holding tap
+//     (g < 2 ? kTapA : kTapB)[s] and channels 8 (g % 2) .. + 7, where kTapA = {0, 1, 2, 6} and
+//     kTapB = {3, 4, 5, 7} (tap B is tap A one row down in steps 0..2, one column right in
+//     step 3); then one 16x16x16 step for tap 8, lane group g holding channels 4 g .. + 3.
+//   1 input channel: one 16x16x16 step, lane group g < 3 holding taps 3 g .. 3 g + 2 (row dy =
+//     g) and a zero, group 3 zeros.
+// BF16 rounding is the hardware's round-to-nearest-even conversion.  The backward convolution
+// with respect to the input is the same kernel with the weights transposed and the taps
+// flipped (packed by cnn_pack_kernel), and its output multiplied by the ReLU mask of the layer
+// below.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -24,6 +34,7 @@ namespace fhtfbp {
 namespace {
 
 typedef __attribute__((__vector_size__(8 * sizeof(short)))) short bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(short)))) short bf16x4;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
 __device__ __forceinline__ uint16_t f2bf(float f) {   // round to nearest even (hardware)
@@ -40,22 +51,59 @@ __device__ __forceinline__ uint2 pack4_bf16(float a, float b, float c, float d) 
   return make_uint2(pack2_bf16(a, b), pack2_bf16(c, d));
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+// ReLU of two packed BF16 values: as 16-bit integers the negative ones (sign bit set) are the
+// negative ones, so a packed integer max with 0 clears them (the same values as the FP32 max
+// before rounding: rounding keeps the sign and maps no positive value to a negative one).
+typedef short short2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t relu_bf16x2(uint32_t w) {
+  return __builtin_bit_cast(uint32_t,
+                            __builtin_elementwise_max(__builtin_bit_cast(short2v, w), short2v{0, 0}));
+}
 
-// Packs FP32 weights w[cout][cin][9] into the B operand order of the kernel:
-// packed[step][lane][j] = Wg[32 step + 8 (lane / 16) + j][lane % 16].  transpose_flip: pack the
+// Taps of the two lane-group halves in the four 16x16x32 steps of a 16-channel input (tap B is
+// tap A one row down in steps 0..2, one column right in step 3); tap 8 follows in a 16x16x16 step.
+__device__ constexpr int kTapA[4] = {0, 1, 2, 6};
+__device__ constexpr int kTapB[4] = {3, 4, 5, 7};
+
+__device__ __forceinline__ f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// Packs FP32 weights w[cout][cin][9] into the A operand order of the kernel (the K order in
+// the header), 512 values per step (16x16x32: packed[step][lane][j] = Wg[kk(step, lane, j)]
+// [lane % 16], j < 8; a 16x16x16 step uses the first 256, j < 4).  transpose_flip: pack the
 // weights of the input-gradient convolution, Wg'[tap][co' = ci][ci' = co] = w[co][ci][8 - tap].
 __global__ void cnn_pack_kernel(const float* __restrict__ w, uint16_t* __restrict__ packed,
                                 int cin, int cout, int transpose_flip, int steps) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= steps * 64 * 8) return;
-  const int j = e & 7, lane = (e >> 3) & 63, step = e >> 9;
-  const int n = lane & 15, kk = step * 32 + (lane >> 4) * 8 + j;
   // geometry of the convolution being packed (after the transpose for the backward one)
   const int ci_n = transpose_flip ? cout : cin;    // its input channels
   const int co_n = transpose_flip ? cin : cout;    // its output channels
+  const int step = e >> 9, r = e & 511;
+  int tap = -1, c = 0, n = 0;
+  if (ci_n == 1 || step == 4) {          // 16x16x16 step: lane r / 4 holds K 4 (lane / 16) + j
+    if (r < 256) {
+      const int lane = r >> 2, j = r & 3, g = lane >> 4;
+      n = lane & 15;
+      if (ci_n == 1) {
+        if (g < 3 && j < 3) tap = 3 * g + j;
+      } else {
+        tap = 8;
+        c = 4 * g + j;
+      }
+    }
+  } else {                               // 16x16x32 step s < 4
+    const int lane = r >> 3, j = r & 7, g = lane >> 4;
+    n = lane & 15;
+    tap = g < 2 ? kTapA[step] : kTapB[step];
+    c = (g & 1) * 8 + j;
+  }
   float v = 0.f;
-  if (kk < 9 * ci_n && n < co_n) {
-    const int tap = kk / ci_n, c = kk % ci_n;
+  if (tap >= 0 && n < co_n && c < ci_n) {
     if (!transpose_flip) v = w[(n * cin + c) * 9 + tap];
     else v = w[(c * cin + n) * 9 + (8 - tap)];
   }
@@ -63,7 +111,7 @@ __global__ void cnn_pack_kernel(const float* __restrict__ w, uint16_t* __restric
 }
 
 // CIN in {1, 16} input channels (FP32 image if 1, BF16 NHWC if 16); COUT in {1, 16}.
-// COUT == 16: out16 (BF16 NHWC) = [relu](acc + bias) [* (mask > 0)].
+// COUT == 16: out16 (BF16 NHWC) = [relu]((acc + bias) [* (mask > 0)]).
 // COUT == 1: out32 (FP32) = acc + bias [+ resid].
 template <int CIN, int COUT>
 __global__ void __launch_bounds__(256) cnn_conv_kernel(const float* __restrict__ in32,
@@ -75,7 +123,6 @@ __global__ void __launch_bounds__(256) cnn_conv_kernel(const float* __restrict__
                                                        uint16_t* __restrict__ out16,
                                                        float* __restrict__ out32, int relu, int H,
                                                        int W, long long groups) {
-  constexpr int STEPS = (9 * CIN + 31) / 32;
   const int lane = threadIdx.x & 63;
   const long long gi = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);   // 16-pixel group
   if (gi >= groups) return;
@@ -86,31 +133,34 @@ __global__ void __launch_bounds__(256) cnn_conv_kernel(const float* __restrict__
   const int b = (int)(by / H);
   const int m = lane & 15, kg = lane >> 4;
   const int x = (xg << 4) + m;
+  auto inside = [&](int yy, int xx) { return yy >= 0 && yy < H && xx >= 0 && xx < W; };
   f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  if constexpr (CIN == 16) {
 #pragma unroll
-  for (int step = 0; step < STEPS; ++step) {
-    bf16x8 a;
-    if constexpr (CIN == 16) {
-      const int kk0 = step * 32 + kg * 8;
-      const int tap = kk0 >> 4, c0 = kk0 & 15;
+    for (int s = 0; s < 4; ++s) {
+      const int tap = kg < 2 ? kTapA[s] : kTapB[s];
       const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
-      if (tap < 9 && yy >= 0 && yy < H && xx >= 0 && xx < W) {
-        a = *reinterpret_cast<const bf16x8*>(in16 + (((size_t)b * H + yy) * W + xx) * 16 + c0);
-      } else {
-        a = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
-      }
-    } else {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int tap = kg * 8 + j;
-        const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
-        float v = 0.f;
-        if (tap < 9 && yy >= 0 && yy < H && xx >= 0 && xx < W) v = in32[((size_t)b * H + yy) * W + xx];
-        a[j] = (short)f2bf(v);
-      }
+      bf16x8 a = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+      if (inside(yy, xx))
+        a = *reinterpret_cast<const bf16x8*>(in16 + (((size_t)b * H + yy) * W + xx) * 16 +
+                                             (kg & 1) * 8);
+      acc = mfma32(wop[s * 64 + lane], a, acc);
     }
-    const bf16x8 bw = wop[step * 64 + lane];
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw, a, acc, 0, 0, 0);
+    bf16x4 a = bf16x4{0, 0, 0, 0};
+    if (inside(y + 1, x + 1))
+      a = *reinterpret_cast<const bf16x4*>(in16 + (((size_t)b * H + y + 1) * W + x + 1) * 16 +
+                                           4 * kg);
+    acc = mfma16(reinterpret_cast<const bf16x4*>(wop + 4 * 64)[lane], a, acc);
+  } else {
+    bf16x4 a;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int yy = y + kg - 1, xx = x + j - 1;
+      float v = 0.f;
+      if (kg < 3 && j < 3 && inside(yy, xx)) v = in32[((size_t)b * H + yy) * W + xx];
+      a[j] = (short)f2bf(v);
+    }
+    acc = mfma16(reinterpret_cast<const bf16x4*>(wop)[lane], a, acc);
   }
   // lane (m, kg): pixel x, channels 4 kg .. 4 kg + 3
   const size_t pix = ((size_t)b * H + y) * W + x;
@@ -119,10 +169,11 @@ __global__ void __launch_bounds__(256) cnn_conv_kernel(const float* __restrict__
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       v[i] = acc[i] + (bias ? bias[4 * kg + i] : 0.f);
-      if (relu) v[i] = fmaxf(v[i], 0.f);
       if (mask && !(bf2f(mask[pix * 16 + 4 * kg + i]) > 0.f)) v[i] = 0.f;
     }
-    *reinterpret_cast<uint2*>(out16 + pix * 16 + 4 * kg) = pack4_bf16(v[0], v[1], v[2], v[3]);
+    uint2 w = pack4_bf16(v[0], v[1], v[2], v[3]);
+    if (relu) w = make_uint2(relu_bf16x2(w.x), relu_bf16x2(w.y));
+    *reinterpret_cast<uint2*>(out16 + pix * 16 + 4 * kg) = w;
   } else {
     if (kg == 0) out32[pix] = acc[0] + (bias ? bias[0] : 0.f) + (resid ? resid[pix] : 0.f);
   }
@@ -225,7 +276,9 @@ __global__ void __launch_bounds__(256) cnn_reduce_kernel(const float* __restrict
 // only h1 and h2 never go to HBM.  A group is 16 consecutive pixels of a region in row-major
 // order; lane (m, kg) of a wave ends with channels 4 kg .. + 3 of pixel m.  In LDS the 16
 // channels of a pixel are split in two planes of 8 (16 bytes per pixel and plane): the 16
-// lanes that read one operand half then read 256 consecutive bytes.
+// lanes that read one operand part then read consecutive words.  With the K order of the
+// header, a lane's operand reads for one group are three per-lane bases plus immediate
+// offsets.
 template <int TH, int TW>
 struct FusedTile {
   static constexpr int XR = TH + 6, XC = TW + 6;         // x region
@@ -239,6 +292,27 @@ struct FusedTile {
   static_assert(H1Px % 16 == 0, "h1 region in whole groups of 16 pixels");
   static_assert(TW % 16 == 0 && OutGroups % 8 == 0, "output groups pair up");
 };
+
+// A 16-channel layer's operands for the group whose lane m has base pixel q (top-left of its
+// 3 x 3 window) in a region of `cols` columns and planes of `plane` pixels: steps 0..2 read
+// row (kg / 2) at columns 0..2, step 3 row 2 at column kg / 2, the 16x16x16 step pixel (2, 2).
+struct Ops16 {
+  bf16x8 a[4];
+  bf16x4 a4;
+};
+template <int COLS, int PLANE>
+__device__ __forceinline__ Ops16 load_ops16(const uint16_t* src, int q, int kg) {
+  const uint16_t* p = src + q * 8;
+  const uint16_t* pa = p + ((kg & 1) * PLANE + (kg >> 1) * COLS) * 8;
+  const uint16_t* pb = p + ((kg & 1) * PLANE + 2 * COLS + (kg >> 1)) * 8;
+  const uint16_t* pc = p + ((kg >> 1) * PLANE + 2 * COLS + 2) * 8 + (kg & 1) * 4;
+  Ops16 o;
+#pragma unroll
+  for (int s = 0; s < 3; ++s) o.a[s] = *reinterpret_cast<const bf16x8*>(pa + s * 8);
+  o.a[3] = *reinterpret_cast<const bf16x8*>(pb);
+  o.a4 = *reinterpret_cast<const bf16x4*>(pc);
+  return o;
+}
 
 template <int TH, int TW>
 __global__ void __launch_bounds__(256) cnn_fused_kernel(const float* __restrict__ in,
@@ -260,13 +334,15 @@ __global__ void __launch_bounds__(256) cnn_fused_kernel(const float* __restrict_
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int m = lane & 15, kg = lane >> 4;
-  const bf16x8 w1op = w1[lane];
-  bf16x8 w2op[5], w3op[5];
+  const bf16x4 w1op = reinterpret_cast<const bf16x4*>(w1)[lane];
+  bf16x8 w2op[4], w3op[4];
 #pragma unroll
-  for (int s = 0; s < 5; ++s) {
+  for (int s = 0; s < 4; ++s) {
     w2op[s] = w2[s * 64 + lane];
     w3op[s] = w3[s * 64 + lane];
   }
+  const bf16x4 w2op4 = reinterpret_cast<const bf16x4*>(w2 + 4 * 64)[lane];
+  const bf16x4 w3op4 = reinterpret_cast<const bf16x4*>(w3 + 4 * 64)[lane];
   float bias1[4], bias2[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -274,30 +350,17 @@ __global__ void __launch_bounds__(256) cnn_fused_kernel(const float* __restrict_
     bias2[i] = b2[4 * kg + i];
   }
   const float bias3 = b3[0];
-  // Operand addressing of layers 2 and 3, fixed per lane: step s reads tap 2 s + kg / 2, i.e.
-  // the pixel (tap / 3) rows and (tap % 3) columns from the lane's base pixel, in channel
-  // plane kg % 2.  Tap 9 (step 4, kg >= 2) does not exist: those lanes read their base pixel
-  // and zero it.
-  int o1[5], o2[5];
-#pragma unroll
-  for (int s = 0; s < 5; ++s) {
-    const int tap = 2 * s + (kg >> 1);
-    o1[s] = tap < 9 ? (tap / 3) * T::H1C + tap % 3 : 0;
-    o2[s] = tap < 9 ? (tap / 3) * T::H2C + tap % 3 : 0;
-  }
-  const bool tap9 = (kg >> 1) != 0;
-  // layer 1's operand words: lane group 0 keeps taps 0..7, group 1 tap 8 (first word)
-  const uint32_t lmask0 = kg == 0 ? 0xffffffffu : 0u, lmask8 = kg == 1 ? 0xffffffffu : 0u;
+  // layer 1: lane group kg < 3 reads row kg of the 3 x 3 window, group 3 contributes zeros
+  const int x_row = min(kg, 2) * T::XC;
+  const uint32_t x_keep = kg < 3 ? 0xffffffffu : 0u;
   // The weights and biases are waited for here, before the tile loop: an empty asm that reads
   // them makes the compiler complete their loads once, so that inside the loop no wait for
   // them also waits for the next tile's x loads, which are issued later.
   asm volatile("" ::"v"(w1op), "v"(w2op[0]), "v"(w2op[1]), "v"(w2op[2]), "v"(w2op[3]),
-               "v"(w2op[4]));
-  asm volatile("" ::"v"(w3op[0]), "v"(w3op[1]), "v"(w3op[2]), "v"(w3op[3]), "v"(w3op[4]));
+               "v"(w2op4));
+  asm volatile("" ::"v"(w3op[0]), "v"(w3op[1]), "v"(w3op[2]), "v"(w3op[3]), "v"(w3op4));
   asm volatile("" ::"v"(bias1[0]), "v"(bias1[1]), "v"(bias1[2]), "v"(bias1[3]), "v"(bias2[0]),
                "v"(bias2[1]), "v"(bias2[2]), "v"(bias2[3]), "v"(bias3));
-  const uint16_t* sh1l = sh1 + (kg & 1) * T::H1Px * 8;
-  const uint16_t* sh2l = sh2 + (kg & 1) * T::H2Store * 8;
 
   // The x region of tile tl (three pixels of halo, zero outside the image): loaded into
   // registers, later stored into one of the two LDS buffers.
@@ -337,12 +400,13 @@ __global__ void __launch_bounds__(256) cnn_fused_kernel(const float* __restrict_
     // every region pixel of an interior tile lies in the image: no zeroing to decide
     const bool interior = Y0 >= 3 && X0 >= 3 && Y0 + TH + 3 <= H && X0 + TW + 3 <= W;
 
-    // Bias, ReLU and BF16 of a lane's four channels of region pixel px (zero outside the
-    // image), stored as one 8-byte word into plane kg / 2 of a region of `px_total` pixels.
+    // Bias, BF16, ReLU of a lane's four channels of region pixel px (zero outside the image),
+    // stored as one 8-byte word into plane kg / 2 of a region of `px_total` pixels.
     auto store4 = [&](uint16_t* dst, int px_total, const f32x4& acc, const float* bias, int px,
                       int cols, int oy, int ox) {
-      uint2 w = pack4_bf16(fmaxf(acc[0] + bias[0], 0.f), fmaxf(acc[1] + bias[1], 0.f),
-                           fmaxf(acc[2] + bias[2], 0.f), fmaxf(acc[3] + bias[3], 0.f));
+      uint2 w = pack4_bf16(acc[0] + bias[0], acc[1] + bias[1], acc[2] + bias[2],
+                           acc[3] + bias[3]);
+      w = make_uint2(relu_bf16x2(w.x), relu_bf16x2(w.y));
       if (!interior) {
         const int rr = px / cols, cc = px - rr * cols;
         const int gy = Y0 + oy + rr, gx = X0 + ox + cc;
@@ -351,42 +415,27 @@ __global__ void __launch_bounds__(256) cnn_fused_kernel(const float* __restrict_
       *reinterpret_cast<uint2*>(dst + ((kg >> 1) * px_total + px) * 8 + (kg & 1) * 4) = w;
     };
 
-    // layer 1: x (1 channel) -> h1 (16).  Lane group kg holds taps 8 kg .. 8 kg + 7: kg = 0
-    // taps 0..7, kg = 1 tap 8, the rest zero; every lane reads and selects (no branch).
-    // all nine taps are read by every lane (immediate offsets, no branch), converted in pairs,
-    // and each lane keeps its own words: kg = 0 taps 0..7, kg = 1 tap 8, else zero
-    auto a1 = [&](int p) -> bf16x8 {
+    // layer 1: x (1 channel) -> h1 (16), one 16x16x16 step per group: lane group kg < 3 holds
+    // the three taps of window row kg (converted in pairs) and a zero
+    auto a1 = [&](int p) -> bf16x4 {
       const int r = p / T::H1C, c = p - r * T::H1C;
-      const float* xp = sxc + r * T::XC + c;
-      float tv[9];
-#pragma unroll
-      for (int j = 0; j < 9; ++j) tv[j] = xp[(j / 3) * T::XC + j % 3];
-      uint32_t w[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) w[k] = pack2_bf16(tv[2 * k], tv[2 * k + 1]) & lmask0;
-      w[0] |= pack2_bf16(tv[8], 0.f) & lmask8;
-      return __builtin_bit_cast(bf16x8, make_uint4(w[0], w[1], w[2], w[3]));
+      const float* xp = sxc + r * T::XC + c + x_row;
+      const uint32_t w0 = pack2_bf16(xp[0], xp[1]) & x_keep;
+      const uint32_t w1 = pack2_bf16(xp[2], 0.f) & x_keep;
+      return __builtin_bit_cast(bf16x4, make_uint2(w0, w1));
     };
     // two groups (g, g + 4) at a time, as in the layers below
     for (int g = wave; g < T::H1Groups; g += 8) {
       const int gb = g + 4 < T::H1Groups ? g + 4 : g;
       const int pa = g * 16 + m, pb = gb * 16 + m;
-      const bf16x8 aa = a1(pa), ab = a1(pb);
+      const bf16x4 aa = a1(pa), ab = a1(pb);
       f32x4 acca = {0.f, 0.f, 0.f, 0.f}, accb = {0.f, 0.f, 0.f, 0.f};
-      acca = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1op, aa, acca, 0, 0, 0);
-      accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1op, ab, accb, 0, 0, 0);
+      acca = mfma16(w1op, aa, acca);
+      accb = mfma16(w1op, ab, accb);
       store4(sh1, T::H1Px, acca, bias1, pa, T::H1C, -2, -2);
       store4(sh1, T::H1Px, accb, bias1, pb, T::H1C, -2, -2);
     }
     __syncthreads();   // h1 complete; the previous tile's layer 3 is done with h2
-
-    // The activation operand of step s for base pixel index q of a 16-channel region (lane
-    // plane `src`, per-lane tap offsets `o`): K = tap * 16 + channel; zero past the ninth tap.
-    auto a16 = [&](const uint16_t* src, const int* o, int q, int s) -> bf16x8 {
-      bf16x8 a = *reinterpret_cast<const bf16x8*>(src + (q + o[s]) * 8);
-      if (s == 4 && tap9) a = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
-      return a;
-    };
 
     // layer 2: h1 (16) -> h2 (16).  A wave takes two groups at a time (its groups g and g + 4;
     // the second repeats the first when there is none): their operands load together and the
@@ -396,19 +445,16 @@ __global__ void __launch_bounds__(256) cnn_fused_kernel(const float* __restrict_
       const int pa = g * 16 + m, pb = gb * 16 + m;           // < H2Store
       const int qa = min(pa, T::H2Px - 1), qb = min(pb, T::H2Px - 1);
       const int ra = qa / T::H2C, ca = qa - ra * T::H2C, rb = qb / T::H2C, cb = qb - rb * T::H2C;
-      const int ba = ra * T::H1C + ca, bb = rb * T::H1C + cb;   // base pixels in the h1 region
-      bf16x8 aa[5], ab[5];
-#pragma unroll
-      for (int s = 0; s < 5; ++s) {
-        aa[s] = a16(sh1l, o1, ba, s);
-        ab[s] = a16(sh1l, o1, bb, s);
-      }
+      const Ops16 oa = load_ops16<T::H1C, T::H1Px>(sh1, ra * T::H1C + ca, kg);
+      const Ops16 ob = load_ops16<T::H1C, T::H1Px>(sh1, rb * T::H1C + cb, kg);
       f32x4 acca = {0.f, 0.f, 0.f, 0.f}, accb = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int s = 0; s < 5; ++s) {
-        acca = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2op[s], aa[s], acca, 0, 0, 0);
-        accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2op[s], ab[s], accb, 0, 0, 0);
+      for (int s = 0; s < 4; ++s) {
+        acca = mfma32(w2op[s], oa.a[s], acca);
+        accb = mfma32(w2op[s], ob.a[s], accb);
       }
+      acca = mfma16(w2op4, oa.a4, acca);
+      accb = mfma16(w2op4, ob.a4, accb);
       store4(sh2, T::H2Store, acca, bias2, pa, T::H2C, -1, -1);
       store4(sh2, T::H2Store, accb, bias2, pb, T::H2C, -1, -1);
     }
@@ -419,20 +465,18 @@ __global__ void __launch_bounds__(256) cnn_fused_kernel(const float* __restrict_
     // the residual; a group is 16 pixels of a tile row, two groups (g, g + 4) per wave at a time
     float* dst = out + (size_t)b * H * W;
     for (int g = wave; g < T::OutGroups; g += 8) {
-      bf16x8 aa[5], ab[5];
       const int ra = g / (TW / 16), ca = (g % (TW / 16)) * 16 + m;
       const int rb = (g + 4) / (TW / 16), cb = ((g + 4) % (TW / 16)) * 16 + m;
-#pragma unroll
-      for (int s = 0; s < 5; ++s) {
-        aa[s] = a16(sh2l, o2, ra * T::H2C + ca, s);
-        ab[s] = a16(sh2l, o2, rb * T::H2C + cb, s);
-      }
+      const Ops16 oa = load_ops16<T::H2C, T::H2Store>(sh2, ra * T::H2C + ca, kg);
+      const Ops16 ob = load_ops16<T::H2C, T::H2Store>(sh2, rb * T::H2C + cb, kg);
       f32x4 acca = {0.f, 0.f, 0.f, 0.f}, accb = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int s = 0; s < 5; ++s) {
-        acca = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3op[s], aa[s], acca, 0, 0, 0);
-        accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3op[s], ab[s], accb, 0, 0, 0);
+      for (int s = 0; s < 4; ++s) {
+        acca = mfma32(w3op[s], oa.a[s], acca);
+        accb = mfma32(w3op[s], ob.a[s], accb);
       }
+      acca = mfma16(w3op4, oa.a4, acca);
+      accb = mfma16(w3op4, ob.a4, accb);
       if (kg == 0) {
         const int gya = Y0 + ra, gxa = X0 + ca, gyb = Y0 + rb, gxb = X0 + cb;
         if (gya < H && gxa < W)

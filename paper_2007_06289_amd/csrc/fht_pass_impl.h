@@ -924,12 +924,20 @@ __device__ __forceinline__ float lanes_shift_up_any(float v) {
 
 // The stage gives every wave one unit and the blocks first, first + step, ... of it (so the
 // waves must outnumber the units), at most kStageMaxBlocks of them.
-__device__ __forceinline__ bool stage4_fits(const PassArgs& A) {
+__host__ __device__ inline bool stage4_fits(const PassArgs& A, int threads) {
   const int N = 1 << A.log2n;
-  const int waves = blockDim.x >> 6, units = (1 << A.log2r) >> 2;
+  const int waves = threads >> 6, units = (1 << A.log2r) >> 2;
   if (waves < units) return false;
   const int nb = (N + 60) / 61, step = waves / units;
   return (nb + step - 1) / step <= kStageMaxBlocks;
+}
+
+// Whether a first pass of order K runs the levels after level 0 (done in the filter when a row
+// has at most 32 chunks) as radix-4 stages, the last of which stores the tile; otherwise every
+// level streams and the tile is written out from LDS.  The host picks the kernel by it.
+__host__ __device__ inline bool first_pass_stages(const PassArgs& A, int threads, int K) {
+  const int l = (K > 0 && A.log2c <= 5) ? 1 : 0;
+  return A.levels - l >= 2 && stage4_fits(A, threads);
 }
 
 // IN_SKEW: the stage reads skewed rows (from the filter or a streaming level); later stages
@@ -1015,6 +1023,11 @@ __device__ __forceinline__ void stage4(const PassArgs& A, float* S, int l, int r
   __syncthreads();
 }
 
+// A block of stage4_store past the wave's last, and lanes that only feed their neighbours'
+// shifts, store to this byte offset, beyond any slice: the hardware drops out-of-range buffer
+// stores, so the stores need no branch.
+constexpr int kDropOffset = 0x40000000;
+
 // The last stage of the first pass: as stage4, but each block's outputs go straight to HBM
 // (row brev(rho) 2^k_lo + v of the class, rotated by sig0 + v brev(rho)), one 4-byte store per
 // lane and row, as soon as they are computed.  Nothing is written back to LDS, so the stage
@@ -1072,9 +1085,12 @@ __device__ __forceinline__ void stage4_store(const PassArgs& A, const float* S, 
   const float* q3 = p3 + (cb + e + d23);
   auto blocks = [&](auto inner_tag) {
     constexpr bool INNER = decltype(inner_tag)::value;
+  // every wave issues all kStageMaxBlocks blocks' stores (kTileStores per lane): blocks past
+  // the wave's last, lanes 0..2 (they only feed their neighbours' shifts) and columns past N
+  // store to kDropOffset
 #pragma unroll
   for (int j = 0; j < kStageMaxBlocks; ++j) {
-    if (j < nbw) {
+    {
       const bool inner = INNER && j >= 1 && j <= kStageInnerLast;
       const int blk = first + j * step;
       const int c = blk * 61 - 3 + lane;
@@ -1101,13 +1117,16 @@ __device__ __forceinline__ void stage4_store(const PassArgs& A, const float* S, 
       const float B2 = A0 + lanes_shift_up_any(A2e);
       const float B1 = A1 + t;
       const float B3 = A1 + lanes_shift_up_any(t);
-      if (lane >= 3 && c < N) {
-        const int c4 = c * 4;
-        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(B0), out, (c4 + y0) & m4, so0, 0);
-        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(B1), out, (c4 + y1) & m4, so1, 0);
-        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(B2), out, (c4 + y2) & m4, so2, 0);
-        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(B3), out, (c4 + y3) & m4, so3, 0);
-      }
+      const bool keep = j < nbw && lane >= 3 && c < N;
+      const int c4 = c * 4;
+      __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(B0), out,
+                                            keep ? (c4 + y0) & m4 : kDropOffset, so0, 0);
+      __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(B1), out,
+                                            keep ? (c4 + y1) & m4 : kDropOffset, so1, 0);
+      __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(B2), out,
+                                            keep ? (c4 + y2) & m4 : kDropOffset, so2, 0);
+      __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(B3), out,
+                                            keep ? (c4 + y3) & m4 : kDropOffset, so3, 0);
     }
   }
   };
@@ -1320,7 +1339,10 @@ __device__ __forceinline__ float4 load4_rotated(const float* row, int x, int o, 
 // the second half goes out before the levels; levels 1 .. F - 1 run as radix-4 stages (an odd
 // one streams first), the last of which stores the tile to HBM itself.  The loads of the next
 // tile are in flight through all of it.
-template <int L, int K, int NBLK, bool WIDE = false, bool REM = false>
+// STAGES: the levels run as radix-4 stages (first_pass_stages).  The two level forms are
+// separate kernels: with both in one, the compiler's waits at the top of the tile loop also
+// count the previous tile's stores (see prefetch_landed).
+template <int L, int K, int NBLK, bool WIDE = false, bool REM = false, bool STAGES = true>
 __global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
   extern __shared__ float S[];
   const int T = blockDim.x, tid = threadIdx.x;
@@ -1368,8 +1390,20 @@ __global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
       }
     }
   };
+  // The prefetched rows are marked as landed (an empty asm that redefines them) before a tile's
+  // stores are issued: the compiler waits for their loads there, where only loads were issued
+  // after them, and at the next deposit (or where it reuses their registers) finds nothing to
+  // wait for.  Left to itself it would wait there with a count that, across the loop, cannot
+  // tell the loads from the stores issued after them, and so hold the next tile until this
+  // tile's stores had drained.
+  auto prefetch_landed = [&]() {
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+      asm volatile("" : "+v"(pre[k].x), "+v"(pre[k].y), "+v"(pre[k].z), "+v"(pre[k].w));
+  };
   issue(tl, 0);
   issue(tl, 1);
+  prefetch_landed();
   for (; tl < A.total_tiles; tl += gridDim.x) {
     // the thread index is passed through an empty asm once per tile, so per-thread addresses
     // are recomputed each iteration instead of being held in registers across the whole loop
@@ -1410,53 +1444,51 @@ __global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
     // the scan's exchange area (rows of more than 64 chunks) after the tile and the streaming
     // copies
     float* xs = S + (pass_lds_bytes(A) >> 2);
+    // the next tile's loads (the last tile of a block reloads itself instead of branching)
+    const int tn = more ? tl + (int)gridDim.x : tl;
     if constexpr (K > 0) {
-      // the first half of the next tile's loads, one every 8 recursion steps (the last tile
-      // of a block reloads itself instead of branching: no branch splits the filter's code)
-      const int tn = more ? tl + (int)gridDim.x : tl;
+      // the first half one every 8 recursion steps
       level0 = filter_tile_aligned<K, WIDE, REM>(A, S, xs, q, row0, ct, [&](int s) {
         if ((s & 7) == 0) issue_one(tn, s >> 3);
       });
     } else {
-      if (more) issue(tl + gridDim.x, 0);
+      issue(tn, 0);
     }
-    if (more) issue(tl + gridDim.x, 1);
+    issue(tn, 1);
     const int sig0 = (K > 0) ? window_start_of(row0, A.log2n, A.windowed) : 0;
-    // levels: an odd one streams, the rest go two at a time; the last pair stores the tile
-    bool stored = false;     // the last stage stored the tile to HBM itself
+    // levels: an odd one streams, the rest go two at a time and the last pair stores the tile;
+    // without radix-4 stages every level streams and the tile is written out from LDS
+    float* dst = A.out + (size_t)bq * N * N;
     // the unmasked interior blocks add code that higher orders pay for in spilled registers
     constexpr bool kInner = K <= 2;
-    {
-      float* copy = S + (1 << A.log2r) * A.rs;
-      int l = level0 ? 1 : 0;
-      const bool radix4 = (F - l >= 2) && stage4_fits(A);
-      if (!radix4 || ((F - l) & 1)) {
-        const int stop = radix4 ? l + 1 : F;
-        for (; l < stop; ++l) {
-          level_stream_rot<NBLK, (K > 0)>(A, S, copy, l, row0);
-          __syncthreads();
-        }
+    float* copy = S + (1 << A.log2r) * A.rs;
+    int l = level0 ? 1 : 0;
+    if constexpr (STAGES) {
+      if ((F - l) & 1) {
+        level_stream_rot<NBLK, (K > 0)>(A, S, copy, l, row0);
+        __syncthreads();
+        ++l;
       }
-      for (bool first_stage = true; l < F; l += 2, first_stage = false) {
-        if (l + 2 == F) {
-          float* dst = A.out + (size_t)bq * N * N;
-          if (first_stage)
-            stage4_store<(K > 0), true, kInner>(A, S, l, row0, sig0, v, dst, k_lo);
-          else
-            stage4_store<(K > 0), false, kInner>(A, S, l, row0, sig0, v, dst, k_lo);
-          stored = true;
-        } else {
-          if (first_stage) stage4<(K > 0), true, kInner>(A, S, l, row0);
-          else stage4<(K > 0), false, kInner>(A, S, l, row0);
-        }
+      bool first_stage = true;
+      for (; l + 2 < F; l += 2, first_stage = false) {
+        if (first_stage) stage4<(K > 0), true, kInner>(A, S, l, row0);
+        else stage4<(K > 0), false, kInner>(A, S, l, row0);
       }
-    }
-    float* dst = A.out + (size_t)bq * N * N;
-    int stid = tid;
-    asm volatile("" : "+v"(stid));
-    // as in the deposit, a wave's 256 values lie in one row: row, output row and rotation are
-    // wave-uniform, only the column is per lane
-    if (!stored) {
+      prefetch_landed();   // the next tile's rows, before this tile's stores
+      if (first_stage)
+        stage4_store<(K > 0), true, kInner>(A, S, l, row0, sig0, v, dst, k_lo);
+      else
+        stage4_store<(K > 0), false, kInner>(A, S, l, row0, sig0, v, dst, k_lo);
+    } else {
+      for (; l < F; ++l) {
+        level_stream_rot<NBLK, (K > 0)>(A, S, copy, l, row0);
+        __syncthreads();
+      }
+      // as in the deposit, a wave's 256 values lie in one row: row, output row and rotation
+      // are wave-uniform, only the column is per lane
+      prefetch_landed();   // the next tile's rows, before this tile's stores
+      int stid = tid;
+      asm volatile("" : "+v"(stid));
 #pragma unroll
       for (int k = 0; k < NV; ++k) {
         const int e4 = (stid + k * T) << 2;
@@ -2383,15 +2415,23 @@ hipError_t launch_lk(const PassArgs& a, int batch, hipStream_t stream) {
 
 // The first-pass kernel of order K, with the numerator's remainder term when the plan's
 // coefficients have one (orders >= 2, unbalanced numerators).
+template <int L, int K, int NBLK, bool WIDE, bool STAGES>
+hipError_t launch_first_ks(const PassArgs& a, int grid, int threads, size_t lds,
+                           hipStream_t stream) {
+  if constexpr (K >= 2) {
+    if (a.rem)
+      return launch_kernel(fht_first_kernel<L, K, NBLK, WIDE, true, STAGES>, a, grid, threads,
+                           lds, stream);
+  }
+  return launch_kernel(fht_first_kernel<L, K, NBLK, WIDE, false, STAGES>, a, grid, threads, lds,
+                       stream);
+}
 template <int L, int K, int NBLK, bool WIDE>
 hipError_t launch_first_k(const PassArgs& a, int grid, int threads, size_t lds,
                           hipStream_t stream) {
-  if constexpr (K >= 2) {
-    if (a.rem)
-      return launch_kernel(fht_first_kernel<L, K, NBLK, WIDE, true>, a, grid, threads, lds,
-                           stream);
-  }
-  return launch_kernel(fht_first_kernel<L, K, NBLK, WIDE, false>, a, grid, threads, lds, stream);
+  if (first_pass_stages(a, threads, K))
+    return launch_first_ks<L, K, NBLK, WIDE, true>(a, grid, threads, lds, stream);
+  return launch_first_ks<L, K, NBLK, WIDE, false>(a, grid, threads, lds, stream);
 }
 
 template <int L, int NBLK>

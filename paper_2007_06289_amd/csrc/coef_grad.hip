@@ -22,7 +22,7 @@ __device__ __forceinline__ int skew(int s, int log2l) { return s + (s >> log2l);
 // the chunk in the direction of the recursion (base - 1 - k, or base + L + k).
 template <int L, int K, int NB, int DIR, typename In>
 __device__ void chunk_rec(In in, const float* bk, const float* ak, const float* phi, int c, int C,
-                          int base, float (&y)[L], float (&ent)[K]) {
+                          int levels, int base, float (&y)[L], float (&ent)[K]) {
   float st[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) st[k] = 0.f;
@@ -42,7 +42,7 @@ __device__ void chunk_rec(In in, const float* bk, const float* ak, const float* 
   float tv[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) tv[k] = st[k];
-  for (int j = 0; (1 << j) < C; ++j) {
+  for (int j = 0; (1 << j) < C && j < levels; ++j) {   // the plan's scan depth
     const int d = 1 << j;
     float u[K];
 #pragma unroll
@@ -134,8 +134,8 @@ __global__ void __launch_bounds__(512) coef_grad_kernel(PassArgs A, const float*
   }
   {
     float yp[L], ep[K], lam[L], el[K];
-    chunk_rec<L, K, K, +1>(xin, bk, ak, phi, c, C, base, yp, ep);
-    chunk_rec<L, K, 1, -1>(gin_, one, ak, phi, c, C, base, lam, el);
+    chunk_rec<L, K, K, +1>(xin, bk, ak, phi, c, C, A.scan_levels, base, yp, ep);
+    chunk_rec<L, K, 1, -1>(gin_, one, ak, phi, c, C, A.scan_levels, base, lam, el);
 #pragma unroll
     for (int i = 0; i < L; ++i) {
 #pragma unroll
@@ -150,8 +150,8 @@ __global__ void __launch_bounds__(512) coef_grad_kernel(PassArgs A, const float*
   }
   {
     float ym[L], em[K], mu[L], eu[K];
-    chunk_rec<L, K, K, -1>(xin, bk, ak, phi, c, C, base, ym, em);
-    chunk_rec<L, K, 1, +1>(gin_, one, ak, phi, c, C, base, mu, eu);
+    chunk_rec<L, K, K, -1>(xin, bk, ak, phi, c, C, A.scan_levels, base, ym, em);
+    chunk_rec<L, K, 1, +1>(gin_, one, ak, phi, c, C, A.scan_levels, base, mu, eu);
 #pragma unroll
     for (int i = 0; i < L; ++i) {
 #pragma unroll

@@ -246,7 +246,7 @@ __device__ void filter_tile(const PassArgs& A, float* S, int q, int row0) {
       tc[k] = stc[k];
       ta[k] = sta[k];
     }
-    for (int jj = 0; (1 << jj) < C; ++jj) {
+    for (int jj = 0; (1 << jj) < C && jj < A.scan_levels; ++jj) {
       const int d = 1 << jj;
       float uc[K], ua[K];
 #pragma unroll
@@ -426,7 +426,7 @@ __device__ bool filter_tile_aligned(const PassArgs& A, float* S, float* xs, int 
     // level below goes across them)
     const int W = WIDE ? 64 : C;
     const int cw = c & (W - 1);
-    for (int jj = 0; (1 << jj) < W; ++jj) {
+    for (int jj = 0; (1 << jj) < W && jj < A.scan_levels; ++jj) {
       const int d = 1 << jj;
       float uc[K], ua[K];
 #pragma unroll

@@ -33,6 +33,9 @@ struct fbp_plan_s {
   // response at zero frequency exact in float32; `rem`: some group's sum(b) is not zero, so
   // the kernels add the remainder term
   bool rem = false;
+  // levels of the filter's chunk-state scan for the plan's chunks and for 32-sample chunks
+  // (scan_depth); a change makes captured graphs stale
+  int scan_levels = kScanLevels, scan_levels32 = kScanLevels;
   int coef_stride = 0;
   float* d_coef = nullptr;
   // N = 4096: the filter's own chunks are 64 samples (C = 64), while the persistent first pass
@@ -207,14 +210,39 @@ bool numerator_remainder(const fbp_plan_s* p) {
   return false;
 }
 
+// Levels of the chunk-state scan one group needs.  After j levels a chunk's end state holds
+// the local end states of the 2^j chunks up to it, each carried through Phi^(L m); the chunks
+// 2^j and more back are left out.  With n_j = ||Phi^(L 2^j)|| (infinity norm) and n_0 < 1,
+// what is left out is at most n_j / (1 - n_0) times the largest local end state
+// (||Phi^(L (2^j + i))|| <= n_j n_0^i): the depth is the first j where that is below 2^-30,
+// far under the float32 rounding of the states.  Without n_0 < 1, every level.
+int scan_depth(const double* phi /* [kScanLevels][K][K] */, int K) {
+  double n[kScanLevels];
+  for (int j = 0; j < kScanLevels; ++j) {
+    double m = 0.0;
+    for (int r = 0; r < K; ++r) {
+      double row = 0.0;
+      for (int c = 0; c < K; ++c) row += fabs(phi[(j * K + r) * K + c]);
+      m = row > m ? row : m;
+    }
+    n[j] = m;
+  }
+  if (!(n[0] < 1.0)) return kScanLevels;
+  for (int j = 0; j < kScanLevels; ++j)
+    if (n[j] / (1.0 - n[0]) <= 0x1p-30) return j;
+  return kScanLevels;
+}
+
 // One coefficient table for chunks of L samples: per group b[K], a[K], Phi^(L 2^j) for
 // j < kScanLevels, the homogeneous responses h_k[0 .. L-1], and the first-difference
-// numerator's taps c[0 .. K-2] and remainder s.
-int fill_coefficients(const fbp_plan_s* p, int L, int stride, std::vector<float>& host) {
+// numerator's taps c[0 .. K-2] and remainder s.  *depth: the scan levels the groups need.
+int fill_coefficients(const fbp_plan_s* p, int L, int stride, std::vector<float>& host,
+                      int* depth) {
   const int K0 = p->order, G = p->groups;
   const int K = kernel_order(K0);   // taps K0..K-1 are zero
   host.assign((size_t)G * stride, 0.f);
   std::vector<double> phi(kScanLevels * K * K), hom((size_t)K * L);
+  *depth = K > 0 ? 0 : kScanLevels;
   for (int g = 0; g < G; ++g) {
     std::vector<double> bg(K, 0.0), ag(K, 0.0);
     for (int k = 0; k < K0; ++k) {
@@ -230,6 +258,10 @@ int fill_coefficients(const fbp_plan_s* p, int L, int stride, std::vector<float>
     transition_powers(ag.data(), K, L, phi.data());
     for (int i = 0; i < kScanLevels * K * K; ++i)
       host[(size_t)g * stride + 2 * K + i] = (float)phi[i];
+    if (K > 0) {
+      const int d = scan_depth(phi.data(), K);
+      *depth = d > *depth ? d : *depth;
+    }
     homogeneous_table(ag.data(), K, L, hom.data());
     for (int i = 0; i < K * L; ++i)
       host[(size_t)g * stride + 2 * K + kScanLevels * K * K + i] = (float)hom[i];
@@ -257,11 +289,17 @@ int upload_coefficients(fbp_plan_s* p) {
   // the remainder term is compiled into the kernels a graph captured: a change makes such
   // graphs stale, as a schedule change does
   const bool rem = numerator_remainder(p);
-  if (rem != p->rem) p->generation += 1;
-  p->rem = rem;
-  int rc = fill_coefficients(p, 1 << p->log2l, p->coef_stride, host);
-  if (rc == FBP_OK && p->d_coef32) rc = fill_coefficients(p, 32, p->coef_stride32, host32);
+  int depth = kScanLevels, depth32 = kScanLevels;
+  int rc = fill_coefficients(p, 1 << p->log2l, p->coef_stride, host, &depth);
+  if (rc == FBP_OK && p->d_coef32)
+    rc = fill_coefficients(p, 32, p->coef_stride32, host32, &depth32);
   if (rc != FBP_OK) return rc;
+  // so is the scan depth (a kernel argument)
+  if (rem != p->rem || depth != p->scan_levels || depth32 != p->scan_levels32)
+    p->generation += 1;
+  p->rem = rem;
+  p->scan_levels = depth;
+  p->scan_levels32 = depth32;
   if (hipStreamSynchronize(p->stream) != hipSuccess) return FBP_EDEVICE;
   if (hipMemcpy(p->d_coef, host.data(), host.size() * sizeof(float), hipMemcpyHostToDevice) !=
       hipSuccess)
@@ -401,6 +439,7 @@ PassArgs base_args(const fbp_plan_s* p) {
   A.sigma = p->d_sigma;
   A.windowed = (p->flags & FBP_ZERO_WINDOW) ? 0 : 1;
   A.rem = p->rem ? 1 : 0;
+  A.scan_levels = p->scan_levels;
   return A;
 }
 
@@ -417,6 +456,7 @@ bool first_pass_args(const fbp_plan_s* p, PassArgs& A) {
     F.rs = p->n + (p->n >> 5);
     F.coef = p->d_coef32;
     F.coef_stride = p->coef_stride32;
+    F.scan_levels = p->scan_levels32;
   }
   const size_t lds = pass_lds_bytes(F) + first_xchg_floats(F) * sizeof(float);
   if (!pass_streams(F) || !first_pass_supported(F) || lds > (size_t)kLdsBudget) return false;

@@ -52,6 +52,9 @@ struct PassArgs {
   int total_tiles;     // persistent passes: tiles over the whole batch
   int windowed;        // 1: rows start at the window start below, 0: at shift 0
   int rem;             // 1: the first-difference numerator has a remainder s x[i] (sum(b) != 0)
+  int scan_levels;     // levels of the chunk-state scan the filter runs (<= kScanLevels): the
+                       // contributions of chunks 2^scan_levels or more back, which the scan
+                       // leaves out, are below 2^-30 of the chunk states in every group
 };
 
 // Fourth word of a raw buffer resource on gfx9-family devices (32-bit data, no swizzle).

@@ -179,6 +179,40 @@ def test_reconstruct_matches_oracle(gpu_lib, N, B, order):
     assert _max_rel(got, ref) < 10 * RTOL_RMSE
 
 
+def _fp32_bar(a):
+    """The float32 bar of a recursive filter: the relative error a float32 recursion carries,
+    its per-step rounding (2^-24) amplified by the l1 norm of the all-pole part's impulse
+    response (the noise gain of 1/A(z)), twice over; never below RTOL_RMSE.  For poles close
+    to 1 (the order-4 frequency-domain fit: 0.9946 and 0.9357, DC gain 1/A(1) about 4000)
+    this is well above 1e-5: a sequential float32 recursion of that filter in the same
+    first-difference form lands 2.3e-4 from the FP64 result at N = 512."""
+    h = np.zeros(1 << 16)
+    h[0] = 1.0
+    for n in range(1, len(h)):
+        h[n] = -sum(a[k] * h[n - 1 - k] for k in range(min(len(a), n)))
+    return max(RTOL_RMSE, 2.0 * 2.0 ** -24 * float(np.abs(h).sum()))
+
+
+@pytest.mark.parametrize("N,order,frequency", [(1024, 2, False), (1024, 4, False), (512, 4, False),
+                                               (1024, 3, True), (1024, 4, True), (512, 4, True)])
+def test_reconstruct_scan_depths_match_oracle(gpu_lib, N, order, frequency):
+    """The plan runs as many levels of the chunk-state scan as its coefficients need (none for
+    the order-2 time-domain fit, whose chunk transition has norm 3e-11; 3 of 5 for the order-4
+    one; all for the frequency-domain fits, with poles within 1 - 2/L of the unit circle).
+    Each against the FP64 oracle, which filters whole rows, to the filter's float32 bar."""
+    api = gpu_lib
+    P = _phantom_lino(N, 2, seed=N + 7 * order + frequency)
+    b, a, _ = api.fbp_fit_ramp_iir(order, N if frequency else min(N, 512), dc_zero=True,
+                                   frequency=frequency)
+    with api.fbp_plan(N, 2, b, a) as plan:
+        got = api.fbp_reconstruct(plan, P.cuda())
+        torch.cuda.synchronize()
+    ref = O.fbp_fht(P.to(torch.float64), torch.tensor(b), torch.tensor(a))
+    bar = _fp32_bar(a)
+    assert _rel_rmse(got, ref) < bar
+    assert _max_rel(got, ref) < 10 * bar
+
+
 @pytest.mark.parametrize("N,order,balanced", [(512, 5, True), (512, 6, False), (512, 8, True),
                                               (1024, 5, False), (1024, 6, True),
                                               (1024, 8, False), (1024, 8, True)])

@@ -1459,8 +1459,9 @@ __global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
     // levels: an odd one streams, the rest go two at a time and the last pair stores the tile;
     // without radix-4 stages every level streams and the tile is written out from LDS
     float* dst = A.out + (size_t)bq * N * N;
-    // the unmasked interior blocks add code that higher orders pay for in spilled registers
-    constexpr bool kInner = K <= 2;
+    // the unmasked interior blocks add code: orders up to 4 have the registers for it (order
+    // 8 would spill)
+    constexpr bool kInner = K <= 4;
     float* copy = S + (1 << A.log2r) * A.rs;
     int l = level0 ? 1 : 0;
     if constexpr (STAGES) {

@@ -321,7 +321,18 @@ __device__ bool filter_tile_aligned(const PassArgs& A, float* S, float* xs, int 
   int tid = threadIdx.x;
   asm volatile("" : "+v"(tid));
   const int C = 1 << A.log2c;
-  const int r = tid >> A.log2c, c = tid & (C - 1);
+  const int lane = tid & 63;
+  // Rows of 32 chunks (ILV): the wave's two rows interleave by 16 chunks, lanes 0-15 holding
+  // row 2w's chunks 0-15, lanes 16-31 row 2w + 1's, lanes 32-47 and 48-63 their chunks 16-31,
+  // so that level 0's partner (the same chunk of the other row) is lane ^ 16, as for rows of
+  // 16 chunks.  Otherwise a row's chunks are consecutive lanes.
+  const bool ilv = A.log2c == 5;
+  const int r = ilv ? (((tid >> 6) << 1) | ((lane >> 4) & 1)) : tid >> A.log2c;
+  const int c = ilv ? ((lane & 15) | ((lane >> 5) << 4)) : tid & (C - 1);
+  // the lane of chunk cc of this lane's row (rows within one wave)
+  auto chunk_lane = [&](int cc) -> int {
+    return ilv ? ((cc & 15) | (lane & 16) | ((cc >> 4) << 5)) : (lane & ~(C - 1)) | cc;
+  };
   const int N = 1 << A.log2n;
   const int t = row0 + r;
   const int g = __builtin_amdgcn_readfirstlane(((q * N + t) * A.groups) / (4 * N));
@@ -429,10 +440,13 @@ __device__ bool filter_tile_aligned(const PassArgs& A, float* S, float* xs, int 
     for (int jj = 0; (1 << jj) < W && jj < A.scan_levels; ++jj) {
       const int d = 1 << jj;
       float uc[K], ua[K];
+      // the states of chunks cw - d and cw + d (masked below where they do not exist)
+      const int lu = WIDE ? lane - (cw >= d ? d : 0) : chunk_lane(cw >= d ? cw - d : cw);
+      const int ld = WIDE ? lane + (cw + d < W ? d : 0) : chunk_lane(cw + d < W ? cw + d : cw);
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        uc[k] = __shfl_up(tc[k], d, W);
-        ua[k] = __shfl_down(ta[k], d, W);
+        uc[k] = __shfl(tc[k], lu);
+        ua[k] = __shfl(ta[k], ld);
       }
       cfloat* P = phi + jj * K * K;
       float nc[K], na[K];
@@ -504,10 +518,12 @@ __device__ bool filter_tile_aligned(const PassArgs& A, float* S, float* xs, int 
         else tc[k] += v[k];
       }
     }
+    const int l1u = WIDE ? lane - (cw >= 1 ? 1 : 0) : chunk_lane(cw >= 1 ? cw - 1 : cw);
+    const int l1d = WIDE ? lane + (cw + 1 < W ? 1 : 0) : chunk_lane(cw + 1 < W ? cw + 1 : cw);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const float pc = (W > 1) ? __shfl_up(tc[k], 1, W) : 0.f;
-      const float pa = (W > 1) ? __shfl_down(ta[k], 1, W) : 0.f;
+      const float pc = (W > 1) ? __shfl(tc[k], l1u) : 0.f;
+      const float pa = (W > 1) ? __shfl(ta[k], l1d) : 0.f;
       stc[k] = (c == 0) ? 0.f : (cw == 0 ? ec[k] : pc);
       sta[k] = (c == C - 1) ? 0.f : (cw == W - 1 ? ea[k] : pa);
     }
@@ -536,28 +552,20 @@ __device__ bool filter_tile_aligned(const PassArgs& A, float* S, float* xs, int 
   // and the rows are stored after level 0 (the same additions as the LDS level would do).
   const bool level0 = A.log2c <= 5;
   if (level0) {
-    const int lane = tid & 63;
     const bool upper = (r & 1) != 0;
     float v[L];
 #pragma unroll
     for (int i = 0; i < L; ++i) v[i] = y[i];
     // r1[x - 1] at the start of the chunk: the last value of the previous chunk of this row
-    const float prev = __shfl(v[L - 1], (lane & ~(C - 1)) | ((c - 1) & (C - 1)));
-    // the partner lane is lane ^ C.  For C = 32 and 16 one permlane swap per sample does it:
-    // swapping X = v[i] with Y = (upper ? r1[x - 1] : v[i]) leaves r0[x] in the first output of
-    // every lane and, in the second, r1[x] for the lower row and r1[x - 1] for the upper one,
-    // so each lane's level-0 value is the sum of the two (no LDS traffic, no select after the
-    // swap).  Other C use a shuffle.
-    // (one loop per exchange kind: the choice is made once, not per sample)
-    if (A.log2c == 5) {
-#pragma unroll
-      for (int i = 0; i < L; ++i) {
-        const float yv = upper ? (i == 0 ? prev : v[i - 1]) : v[i];
-        const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]),
-                                                         __float_as_uint(yv), false, false);
-        rp[i] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
-      }
-    } else if (A.log2c == 4) {
+    const float prev = __shfl(v[L - 1], chunk_lane((c - 1) & (C - 1)));
+    // the partner lane is lane ^ 16 for C = 32 (interleaved rows) and 16, lane ^ C otherwise.
+    // For C = 32 and 16 one permlane swap of rows of 16 lanes per sample does it: swapping
+    // X = v[i] with Y = (upper ? r1[x - 1] : v[i]) leaves r0[x] in the first output of every
+    // lane and, in the second, r1[x] for the lower row and r1[x - 1] for the upper one, so each
+    // lane's level-0 value is the sum of the two (no LDS traffic, no select after the swap).
+    // (The 32-lane swap, for rows of consecutive lanes, costs two register copies per sample.)
+    // Other C use a shuffle.
+    if (A.log2c == 4 || ilv) {
 #pragma unroll
       for (int i = 0; i < L; ++i) {
         const float yv = upper ? (i == 0 ? prev : v[i - 1]) : v[i];
@@ -1421,7 +1429,8 @@ __global__ void __launch_bounds__(1024) fht_first_kernel(PassArgs A) {
       // all eight factors in one go (the table has spare floats past row N - 1), no waits in
       // between; lanes pick their row's (C = 128: a wave holds half of row wave / 2)
       cfloat* sc = as_constant(A.scale + row0 + ((wave << 6) >> A.log2c));
-      const int lr = (ltid & 63) >> A.log2c;
+      // (rows of 32 chunks interleave by 16 lanes: see filter_tile_aligned)
+      const int lr = A.log2c == 5 ? (ltid >> 4) & 1 : (ltid & 63) >> A.log2c;
       float f8[8];
 #pragma unroll
       for (int k = 0; k < 8; ++k) f8[k] = sc[k];

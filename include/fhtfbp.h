@@ -92,9 +92,14 @@ int fbp_plan_set_stream(fbp_plan_t plan, void* stream);
 
 /* Replace the recursive-filter coefficients (host arrays shaped as in the description).
  * Synchronises the plan's stream, checks stability, uploads.  Used by the learned filter.
+ * The plan also sets how many levels of the filter's chunk-state scan it runs: the first
+ * depth at which the chunks left out weigh at most 2^-30 of the chunk states, from the norms
+ * of the chunk transition matrices A's coefficients give (no level for fast-decaying poles,
+ * every level for poles near the unit circle).
  * Graphs captured on the plan keep working unless the numerator form changes (every group's
  * new b balanced where some old one was not, or the reverse: the kernels then drop or add the
- * remainder term s); such graphs refuse to launch (FBP_EINVAL) and must be captured again. */
+ * remainder term s) or the scan depth does; such graphs refuse to launch (FBP_EINVAL) and
+ * must be captured again. */
 int fbp_plan_set_coefficients(fbp_plan_t plan, const double* b, const double* a);
 
 /* Row filter alone (Sec. 3, eq 12-13): every linogram row (b, q, t) is read over its window

@@ -211,6 +211,37 @@ def test_graph_sees_new_coefficients_and_refuses_a_new_schedule(gpu_lib):
         g2.close()
 
 
+def test_graph_refuses_a_new_scan_depth(gpu_lib):
+    """The scan depth is a kernel argument: coefficients whose chunk transitions decay slowly
+    (a double pole at 0.95: every scan level) after fast-decaying ones (the order-2 time-domain
+    fit: no level) make a captured graph stale; it refuses to launch, and a recapture gives
+    the eager result, which matches the FP64 oracle."""
+    api = gpu_lib
+    N = 256
+    lino = _lino(N, 2, seed=8)
+    img = torch.empty((2, N, N), device="cuda")
+    with api.fbp_plan(N, 2, *_coef()) as plan:
+        g = api.fbp_graph_create([plan], [lino], [img])
+        g.launch()
+        torch.cuda.synchronize()
+        b1 = np.array([[0.12, -0.12]])
+        a1 = np.array([[-1.9, 0.9025]])
+        api.fbp_plan_set_coefficients(plan, b1, a1)
+        with pytest.raises(api.FbpError) as e:
+            g.launch()
+        assert e.value.code == api.FBP_EINVAL
+        g.close()
+        want = api.fbp_reconstruct(plan, lino)
+        g2 = api.fbp_graph_create([plan], [lino], [img])
+        g2.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(img, want)
+        g2.close()
+    ref = O.fbp_fht(lino.cpu().double(), torch.tensor(b1[0]), torch.tensor(a1[0]))
+    # 2^-24 times the noise gain of 1/(1 - 0.95 z^-1)^2 (400), twice over
+    assert _rel(want, ref) < 2 * 2.0 ** -24 * 400
+
+
 def test_empty_graph_and_zero_batches(gpu_lib):
     api = gpu_lib
     g = api.fbp_graph_create([], [], [])

@@ -303,6 +303,18 @@ int fbp_plan_set_schedule(fbp_plan_t plan, const int32_t* levels, int32_t passes
  * NULL. */
 int fbp_plan_schedule_info(fbp_plan_t plan, int32_t* log2w, int32_t* first_max);
 
+/* How the plan's row filter runs (Sec. 3, eq 9-13), any pointer may be NULL: `chunk` the
+ * samples per chunk of the chunked recursion; `scan_levels` the levels of the chunk-state
+ * scan its coefficients need (0 .. 7, the largest over the angle groups; the scan stops at the
+ * first level j where ||Phi^(chunk 2^j)|| / (1 - ||Phi^chunk||), infinity norm, is at most
+ * 2^-30, and runs every level when ||Phi^chunk|| >= 1); `first_levels` the same for the
+ * chunks of the fused first back-projection pass, which are 32 samples at N = 4096 and the
+ * filter's own (first_levels == scan_levels) at every other size; `remainder` 1 when the numerator's taps do not sum to zero within rounding and the
+ * kernels add the remainder term s of B(z) = (1 - z^-1) C(z) + s, else 0.  Each follows the
+ * last fbp_plan_set_coefficients. */
+int fbp_plan_filter_info(fbp_plan_t plan, int32_t* chunk, int32_t* scan_levels,
+                         int32_t* first_levels, int32_t* remainder);
+
 /* ---- mixed batches and captured execution ------------------------------------------------ */
 typedef struct fbp_graph_s* fbp_graph_t;
 

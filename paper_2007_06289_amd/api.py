@@ -102,6 +102,8 @@ def load_library():
         "fbp_plan_set_schedule": ([vp, ctypes.POINTER(i32), i32, i32], ctypes.c_int),
         "fbp_plan_schedule_info": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32)],
                                    ctypes.c_int),
+        "fbp_plan_filter_info": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                  ctypes.POINTER(i32), ctypes.POINTER(i32)], ctypes.c_int),
         "fbp_reconstruct_many": ([ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                   ctypes.POINTER(i32), i32, vp], ctypes.c_int),
         "fbp_graph_create": ([ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
@@ -203,6 +205,15 @@ class Plan:
         _check(load_library().fbp_plan_schedule_info(self.handle, ctypes.byref(w),
                                                      ctypes.byref(f)), "fbp_plan_schedule_info")
         return self.passes(), int(w.value), int(f.value)
+
+    def filter_info(self) -> dict:
+        """Chunk length, scan levels of the filter's chunks and of the first pass's 32-sample
+        chunks, and whether the numerator's remainder term runs."""
+        v = [ctypes.c_int32() for _ in range(4)]
+        _check(load_library().fbp_plan_filter_info(self.handle, *[ctypes.byref(x) for x in v]),
+               "fbp_plan_filter_info")
+        return {"chunk": int(v[0].value), "scan_levels": int(v[1].value),
+                "first_levels": int(v[2].value), "remainder": bool(v[3].value)}
 
     def set_schedule(self, levels, log2w: int = 0):
         """Regroup the butterfly levels into passes (results are unchanged, bit for bit)."""

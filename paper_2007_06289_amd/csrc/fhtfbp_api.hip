@@ -1211,6 +1211,16 @@ int fbp_plan_schedule_info(fbp_plan_t p, int32_t* log2w, int32_t* first_max) {
   return FBP_OK;
 }
 
+int fbp_plan_filter_info(fbp_plan_t p, int32_t* chunk, int32_t* scan_levels,
+                         int32_t* first_levels, int32_t* remainder) {
+  if (!p) return FBP_EINVAL;
+  if (chunk) *chunk = 1 << p->log2l;
+  if (scan_levels) *scan_levels = p->scan_levels;
+  if (first_levels) *first_levels = p->d_coef32 ? p->scan_levels32 : p->scan_levels;
+  if (remainder) *remainder = p->rem ? 1 : 0;
+  return FBP_OK;
+}
+
 int fbp_reconstruct_many(const fbp_plan_t* plans, const float* const* lino, float* const* img,
                          const int32_t* batch, int32_t count, void* stream) {
   int rc = check_many(plans, lino, img, batch, count);

@@ -193,18 +193,37 @@ def _fp32_bar(a):
     return max(RTOL_RMSE, 2.0 * 2.0 ** -24 * float(np.abs(h).sum()))
 
 
+def _scan_depth(a, L):
+    """Scan levels a chunk of L samples needs: the first j where ||M^(L 2^j)|| / (1 - ||M^L||)
+    is at most 2^-30, M the companion matrix of 1/A(z) over the last K outputs, infinity norm;
+    7 (every level) when ||M^L|| >= 1."""
+    K = len(a)
+    M = np.zeros((K, K))
+    M[0, :] = -np.asarray(a, dtype=np.float64)
+    M[1:, :-1] = np.eye(K - 1)
+    n = [np.abs(np.linalg.matrix_power(M, L << j)).sum(1).max() for j in range(7)]
+    if not n[0] < 1.0:
+        return 7
+    return next((j for j in range(7) if n[j] / (1.0 - n[0]) <= 2.0 ** -30), 7)
+
+
 @pytest.mark.parametrize("N,order,frequency", [(1024, 2, False), (1024, 4, False), (512, 4, False),
                                                (1024, 3, True), (1024, 4, True), (512, 4, True)])
 def test_reconstruct_scan_depths_match_oracle(gpu_lib, N, order, frequency):
     """The plan runs as many levels of the chunk-state scan as its coefficients need (none for
     the order-2 time-domain fit, whose chunk transition has norm 3e-11; 3 of 5 for the order-4
     one; all for the frequency-domain fits, with poles within 1 - 2/L of the unit circle).
-    Each against the FP64 oracle, which filters whole rows, to the filter's float32 bar."""
+    The depth the plan reports is the one numpy finds for its chunks of 32 samples.  Each
+    image against the FP64 oracle, which filters whole rows, to the filter's float32 bar."""
     api = gpu_lib
     P = _phantom_lino(N, 2, seed=N + 7 * order + frequency)
     b, a, _ = api.fbp_fit_ramp_iir(order, N if frequency else min(N, 512), dc_zero=True,
                                    frequency=frequency)
+    want = {(2, False): 0, (4, False): 3}.get((order, frequency), 7)
+    assert _scan_depth(a, 32) == want
     with api.fbp_plan(N, 2, b, a) as plan:
+        assert plan.filter_info() == {"chunk": 32, "scan_levels": want, "first_levels": want,
+                                      "remainder": False}
         got = api.fbp_reconstruct(plan, P.cuda())
         torch.cuda.synchronize()
     ref = O.fbp_fht(P.to(torch.float64), torch.tensor(b), torch.tensor(a))

@@ -221,12 +221,14 @@ def test_graph_refuses_a_new_scan_depth(gpu_lib):
     lino = _lino(N, 2, seed=8)
     img = torch.empty((2, N, N), device="cuda")
     with api.fbp_plan(N, 2, *_coef()) as plan:
+        assert plan.filter_info()["scan_levels"] == 0
         g = api.fbp_graph_create([plan], [lino], [img])
         g.launch()
         torch.cuda.synchronize()
         b1 = np.array([[0.12, -0.12]])
         a1 = np.array([[-1.9, 0.9025]])
         api.fbp_plan_set_coefficients(plan, b1, a1)
+        assert plan.filter_info()["scan_levels"] == 7
         with pytest.raises(api.FbpError) as e:
             g.launch()
         assert e.value.code == api.FBP_EINVAL

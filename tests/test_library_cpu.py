@@ -126,6 +126,7 @@ def test_frequency_fit_reconstructs_closer_to_the_direct_fbp():
 def test_schedule_and_graph_entry_points_reject_bad_arguments(lib):
     assert lib.fbp_plan_set_schedule(None, None, 0, 0) == -1
     assert lib.fbp_plan_schedule_info(None, None, None) == -1
+    assert lib.fbp_plan_filter_info(None, None, None, None, None) == -1
     # an empty mixed batch is a no-op and needs no device
     assert lib.fbp_reconstruct_many(None, None, None, None, 0, None) == 0
     assert lib.fbp_reconstruct_many(None, None, None, None, -1, None) == -1

@@ -184,7 +184,12 @@ __global__ void __launch_bounds__(256) cnn_conv_kernel(const float* __restrict__
 //   dw[co][ci][tap] = sum_p dz[p][co] in[p + off(tap)][ci],   db[co] = sum_p dz[p][co].
 // dz has COUT channels (FP32 image if 1, BF16 NHWC if 16); in has CIN channels (same rule).
 // Each block covers `rows` image rows x 64 columns of one slice and writes its sums to
-// partial[block][COUT * CIN * 9 + COUT].
+// partial[block][COUT * CIN * 9 + COUT].  Thread co * CIN + ci holds the nine taps of the
+// channel pair (co, ci), and the bias of co when ci = 0: along a row, the three input values
+// of each window row slide through registers, so one dz value and three new input values feed
+// nine FMAs.  Every sum runs over the row's pixels in order, rows in order.  The input rows
+// y - 1, y, y + 1 sit in a ring of three LDS rows (row yy in slot (yy + 3) % 3), so each row
+// is staged once; a thread stages 8 channels of a pixel from one 16-byte load.
 template <int CIN, int COUT>
 __global__ void __launch_bounds__(256) cnn_wgrad_kernel(const float* __restrict__ dz32,
                                                         const uint16_t* __restrict__ dz16,
@@ -195,56 +200,107 @@ __global__ void __launch_bounds__(256) cnn_wgrad_kernel(const float* __restrict_
   constexpr int NW = COUT * CIN * 9;
   constexpr int NOUT = NW + COUT;
   constexpr int XS = 64;
-  __shared__ float sdz[XS][COUT];
-  __shared__ float sin_[3][XS + 2][CIN];
+  static_assert(COUT * CIN <= 256, "one thread per channel pair");
+  __shared__ __align__(16) float sdz[XS][COUT];
+  __shared__ __align__(16) float sin_[3][XS + 2][CIN];
   const int cols = W / XS;
   const int rb = blockIdx.x % ((H + rows - 1) / rows);
   const int rest = blockIdx.x / ((H + rows - 1) / rows);
   const int cb = rest % cols, b = rest / cols;
   const int x0 = cb * XS;
-  float acc[(NOUT + 255) / 256];
+  const int tid = threadIdx.x;
+  const int co = tid / CIN, ci = tid % CIN;
+  const bool active = tid < COUT * CIN;
+
+  // 8 BF16 values of one 16-byte load as FP32, stored as two float4
+  auto store8 = [](float* d, const uint4& v) {
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+    float f[8];
 #pragma unroll
-  for (int k = 0; k < (NOUT + 255) / 256; ++k) acc[k] = 0.f;
-  for (int y = rb * rows; y < min(H, (rb + 1) * rows); ++y) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < XS * COUT; e += blockDim.x) {
-      const int xx = e / COUT, c = e % COUT;
-      const size_t pix = ((size_t)b * H + y) * W + x0 + xx;
-      sdz[xx][c] = (COUT == 16) ? bf2f(dz16[pix * 16 + c]) : dz32[pix];
+    for (int k = 0; k < 4; ++k) {
+      f[2 * k] = __uint_as_float(w[k] << 16);
+      f[2 * k + 1] = __uint_as_float(w[k] & 0xffff0000u);
     }
-    for (int e = threadIdx.x; e < 3 * (XS + 2) * CIN; e += blockDim.x) {
-      const int r = e / ((XS + 2) * CIN), rem = e % ((XS + 2) * CIN);
-      const int xx = rem / CIN, c = rem % CIN;
-      const int yy = y + r - 1, gx = x0 + xx - 1;
-      float v = 0.f;
-      if (yy >= 0 && yy < H && gx >= 0 && gx < W) {
-        const size_t pix = ((size_t)b * H + yy) * W + gx;
-        v = (CIN == 16) ? bf2f(in16[pix * 16 + c]) : in32[pix];
+    reinterpret_cast<float4*>(d)[0] = make_float4(f[0], f[1], f[2], f[3]);
+    reinterpret_cast<float4*>(d)[1] = make_float4(f[4], f[5], f[6], f[7]);
+  };
+  // dz of image row y
+  auto stage_dz = [&](int y) {
+    const size_t row = ((size_t)b * H + y) * W + x0;
+    if constexpr (COUT == 16) {
+      if (tid < 2 * XS) {
+        const int xx = tid >> 1, h = tid & 1;
+        store8(&sdz[xx][8 * h], *reinterpret_cast<const uint4*>(dz16 + (row + xx) * 16 + 8 * h));
       }
-      sin_[r][xx][c] = v;
+    } else {
+      if (tid < XS) sdz[tid][0] = dz32[row + tid];
     }
-    __syncthreads();
+  };
+  // input row yy (zero outside the image) into its ring slot, columns x0 - 1 .. x0 + 64
+  auto stage_in = [&](int yy) {
+    float* dst = &sin_[(yy + 3) % 3][0][0];
+    const bool row_in = yy >= 0 && yy < H;
+    const size_t row = ((size_t)b * H + (row_in ? yy : 0)) * W;
+    if constexpr (CIN == 16) {
+      if (tid < 2 * (XS + 2)) {
+        const int xx = tid >> 1, h = tid & 1, gx = x0 + xx - 1;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (row_in && gx >= 0 && gx < W)
+          v = *reinterpret_cast<const uint4*>(in16 + (row + gx) * 16 + 8 * h);
+        store8(dst + xx * 16 + 8 * h, v);
+      }
+    } else {
+      if (tid < XS + 2) {
+        const int gx = x0 + tid - 1;
+        dst[tid] = (row_in && gx >= 0 && gx < W) ? in32[row + gx] : 0.f;
+      }
+    }
+  };
+
+  float acc[9], accb = 0.f;
 #pragma unroll
-    for (int k = 0; k < (NOUT + 255) / 256; ++k) {
-      const int o = threadIdx.x + k * 256;
-      if (o < NW) {
-        const int co = o / (CIN * 9), ci = (o / 9) % CIN, tap = o % 9;
-        const int dy = tap / 3, dx = tap % 3;
-        float s = acc[k];
-        for (int xx = 0; xx < XS; ++xx) s = fmaf(sdz[xx][co], sin_[dy][xx + dx][ci], s);
-        acc[k] = s;
-      } else if (o < NOUT) {
-        const int co = o - NW;
-        float s = acc[k];
-        for (int xx = 0; xx < XS; ++xx) s += sdz[xx][co];
-        acc[k] = s;
+  for (int k = 0; k < 9; ++k) acc[k] = 0.f;
+  const int y0 = rb * rows, y1 = min(H, y0 + rows);
+  stage_in(y0 - 1);
+  stage_in(y0);
+  for (int y = y0; y < y1; ++y) {
+    // the slot of row y + 1 held row y - 2, which the previous row's sums have finished with
+    __syncthreads();
+    stage_in(y + 1);
+    stage_dz(y);
+    __syncthreads();
+    if (active) {
+      const float* r[3];
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy) r[dy] = &sin_[(y + dy + 2) % 3][0][ci];
+      // window row dy at columns xx, xx + 1, xx + 2 (LDS columns of the row, offset by one)
+      float wa[3], wb[3];
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy) {
+        wa[dy] = r[dy][0];
+        wb[dy] = r[dy][CIN];
+      }
+#pragma unroll 8
+      for (int xx = 0; xx < XS; ++xx) {
+        const float d = sdz[xx][co];
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+          const float c = r[dy][(xx + 2) * CIN];
+          acc[3 * dy + 0] = fmaf(d, wa[dy], acc[3 * dy + 0]);
+          acc[3 * dy + 1] = fmaf(d, wb[dy], acc[3 * dy + 1]);
+          acc[3 * dy + 2] = fmaf(d, c, acc[3 * dy + 2]);
+          wa[dy] = wb[dy];
+          wb[dy] = c;
+        }
+        accb += d;
       }
     }
   }
+  if (active) {
+    float* dst = partial + (size_t)blockIdx.x * NOUT;
 #pragma unroll
-  for (int k = 0; k < (NOUT + 255) / 256; ++k) {
-    const int o = threadIdx.x + k * 256;
-    if (o < NOUT) partial[(size_t)blockIdx.x * NOUT + o] = acc[k];
+    for (int k = 0; k < 9; ++k) dst[(co * CIN + ci) * 9 + k] = acc[k];
+    if (ci == 0) dst[NW + co] = accb;
   }
 }
 

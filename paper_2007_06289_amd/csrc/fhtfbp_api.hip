@@ -1098,6 +1098,10 @@ int fbp_cnn_conv(int32_t cin, int32_t cout, const float* in32, const uint16_t* i
   if (!wpacked || (cin == 1 && !in32) || (cin == 16 && !in16) || (cout == 16 && !out16) ||
       (cout == 1 && !out32) || (mask && cout != 16))
     return FBP_EINVAL;
+  // BF16 operands and activations move 8 or 16 bytes at a time
+  if (!aligned16(wpacked) || (in16 && !aligned16(in16)) || (out16 && !aligned16(out16)) ||
+      (mask && !aligned16(mask)))
+    return FBP_EINVAL;
   return launch_cnn_conv(cin, cout, in32, in16, wpacked, bias, mask, resid, out16, out32,
                          relu ? 1 : 0, batch, h, w, (hipStream_t)stream) == hipSuccess
              ? FBP_OK
@@ -1110,6 +1114,7 @@ int fbp_cnn_forward(const float* img, const uint16_t* w1, const float* b1, const
   if (batch < 0 || h < 1 || w < 1) return FBP_EINVAL;
   if (batch == 0) return FBP_OK;
   if (!img || !w1 || !b1 || !w2 || !b2 || !w3 || !b3 || !out) return FBP_EINVAL;
+  if (!aligned16(w1) || !aligned16(w2) || !aligned16(w3)) return FBP_EINVAL;
   if (img == out) return FBP_EINVAL;   // blocks read a halo that other blocks write
   return launch_cnn_fused(img, w1, b1, w2, b2, w3, b3, out, batch, h, w, (hipStream_t)stream) ==
                  hipSuccess
@@ -1132,6 +1137,8 @@ int fbp_cnn_wgrad(int32_t cin, int32_t cout, const float* dz32, const uint16_t* 
   if (!partial || !out || (cout == 1 && !dz32) || (cout == 16 && !dz16) || (cin == 1 && !in32) ||
       (cin == 16 && !in16))
     return FBP_EINVAL;
+  // a pixel's BF16 channels are read 16 bytes at a time
+  if ((dz16 && !aligned16(dz16)) || (in16 && !aligned16(in16))) return FBP_EINVAL;
   return launch_cnn_wgrad(cin, cout, dz32, dz16, in32, in16, partial, out, batch, h, w,
                           (hipStream_t)stream) == hipSuccess
              ? FBP_OK

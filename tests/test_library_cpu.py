@@ -147,3 +147,25 @@ def test_schedule_candidates_are_all_compositions():
             assert all(sum(c) == total and 1 <= len(c) <= parts for c in got)
             assert len(got) == sum(comb(total - 1, j - 1) for j in range(1, parts + 1))
     assert all(max(c) <= 3 for c in compositions(10, 4, 3))
+
+
+def test_cnn_entry_points_reject_unaligned_bf16_buffers(lib):
+    """The network's BF16 activations, gradients and packed weights move 8 or 16 bytes at a
+    time: a pointer off a 16-byte boundary is refused before any launch (the addresses here
+    are never dereferenced)."""
+    ok, odd = 0x10000, 0x10002
+    # weight gradient, 16 -> 16 channels: dz and the input are BF16 NHWC
+    assert lib.fbp_cnn_wgrad(16, 16, None, odd, None, ok, ok, ok, 1, 64, 64, None) == -1
+    assert lib.fbp_cnn_wgrad(16, 16, None, ok, None, odd, ok, ok, 1, 64, 64, None) == -1
+    # convolution: BF16 input, packed weights, output, mask
+    args = dict(in32=None, in16=ok, w=ok, bias=None, mask=None, resid=None, o16=ok, o32=None)
+    for k in ("in16", "w", "o16", "mask"):
+        a = dict(args, **{k: odd})
+        assert lib.fbp_cnn_conv(16, 16, a["in32"], a["in16"], a["w"], a["bias"], a["mask"],
+                                a["resid"], a["o16"], a["o32"], 0, 1, 16, 16, None) == -1
+    # the fused network: packed weights of each layer
+    for i in range(3):
+        w = [ok, ok, ok]
+        w[i] = odd
+        assert lib.fbp_cnn_forward(ok, w[0], ok, w[1], ok, w[2], ok, ok + 64, 1, 16, 16,
+                                   None) == -1

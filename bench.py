@@ -66,12 +66,15 @@ KIND_OF_KERNEL = (("fht_first_kernel", "first"), ("fht_cols_kernel<2>", "last_vh
 
 
 def kernel_source_hash() -> str:
-    """sha256 (16 hex digits) of the HIP sources and headers the pass kernels are built from."""
+    """sha256 (16 hex digits) of the sources the pass kernels are built and launched from: the
+    pass templates and their instantiations, the shared header, and the library's plan and
+    launch code (the network, gradient, direct-FBP, resampling and fitting sources are left
+    out: they change neither the pass kernels nor their launches)."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2007_06289_amd", "csrc")
     for fn in sorted(os.listdir(d)):
-        if fn.endswith((".hip", ".h", ".cpp")):
+        if fn.startswith(("fht_pass", "fht_cols", "fhtfbp_")) and fn.endswith((".hip", ".h")):
             h.update(fn.encode())
             h.update(open(os.path.join(d, fn), "rb").read())
     return h.hexdigest()[:16]

@@ -528,11 +528,12 @@ __device__ bool filter_tile_aligned(const PassArgs& A, float* S, float* xs, int 
       sta[k] = (c == C - 1) ? 0.f : (cw == W - 1 ? ea[k] : pa);
     }
     // carry correction: the carried-in state through the homogeneous response, oldest first
-    // (the table goes through scalar registers 8 steps at a time: the barriers keep the
-    // compiler from loading all of it at once and spilling scalar registers elsewhere)
+    // (the table goes through scalar registers 8 steps at a time, 4 from order 4 on: the
+    // barriers keep the compiler from loading all of it at once and spilling scalar registers
+    // elsewhere)
 #pragma unroll
     for (int s = 0; s < L; ++s) {
-      if ((s & 7) == 0) asm volatile("" ::: "memory");
+      if ((s & (K >= 4 ? 3 : 7)) == 0) asm volatile("" ::: "memory");
       const int i = s, j = L - 1 - s;
       float yc = y[i], ya = y[j];
 #pragma unroll

@@ -97,7 +97,7 @@ def run(n: int = 1024, slices: int = 128, holdout: int = 16, steps: int = 300, b
     rep = {
         "workload": f"{S} noisy slices (I0={i0:g}) N={N}, order {order} x "
                     f"{groups} angle groups, residual network 1-16-16-1; {H} held out",
-        "judge": "direct FBP of the same noisy linogram (exact ramp, exact line positions), "
+        "reference": "direct FBP of the same noisy linogram (exact ramp, exact line positions), "
                  "fbp_direct_linogram on the GPU",
         "rel_rmse_vs_direct_fbp": {"plain": round(e_plain, 5),
                                    "plain_frequency_fit": round(e_plain_f, 5),

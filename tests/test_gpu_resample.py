@@ -95,7 +95,7 @@ def test_padded_grid_handles_objects_outside_the_disc(gpu_lib):
     projections of steep rows are longer than N and fold onto themselves (the cyclic shift
     axis holds objects inside 0.34 N only).  Reconstructed on the 2N grid and cropped, they
     come back about as well as in-disc objects do (measured on the CPU oracle: plain 0.75,
-    padded 0.36 against the direct FBP; the rest is the order-4 filter's own error).  Judged
+    padded 0.36 against the direct FBP; the rest is the order-4 filter's own error).  Measured
     against the FP64 direct FBP of the same sinogram; the composition is also held to the
     FP64 oracle of the same steps."""
     api = gpu_lib

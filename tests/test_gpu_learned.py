@@ -151,6 +151,35 @@ def test_cnn_backward_matches_oracle(gpu_lib):
         assert _rel(g_, r_) < 3e-2, n
 
 
+@pytest.mark.parametrize("cin,cout", [(16, 16), (16, 1), (1, 16)])
+def test_cnn_weight_gradient_matches_fp64(gpu_lib, cin, cout):
+    """fbp_cnn_wgrad alone: dz and the layer input hold BF16 values, so every product is exact
+    in FP32 and only the FP32 sums differ from the FP64 weight gradient (torch's conv2d weight
+    gradient on the CPU) and bias gradient.  Height 40 leaves a partial block of rows, width
+    128 two column blocks; zero padding at every image edge."""
+    api = gpu_lib
+    B, H, W = 2, 40, 128
+    g = torch.Generator().manual_seed(cin * 17 + cout)
+
+    def bf16(*shape):
+        return torch.randn(*shape, generator=g).to(torch.bfloat16)
+
+    dz = bf16(B, H, W, cout)
+    x = bf16(B, H, W, cin)
+    dz_dev = (dz.view(torch.int16) if cout == 16 else dz[..., 0].float()).contiguous().cuda()
+    x_dev = (x.view(torch.int16) if cin == 16 else x[..., 0].float()).contiguous().cuda()
+    got = api.fbp_cnn_wgrad(cin, cout, dz_dev, x_dev).cpu().double()
+    xd = x.double().permute(0, 3, 1, 2)
+    dzd = dz.double().permute(0, 3, 1, 2)
+    gw = torch.nn.grad.conv2d_weight(xd, (cout, cin, 3, 3), dzd, padding=1)
+    gb = dzd.sum(dim=(0, 2, 3))
+    nw = cout * cin * 9
+    # each sum adds B H W products of size ~1 in FP32: a few 2^-24 sqrt(B H W) of its scale
+    scale = math.sqrt(B * H * W)
+    assert float((got[:nw] - gw.reshape(-1)).abs().max()) < 1e-5 * scale
+    assert float((got[nw:] - gb).abs().max()) < 1e-5 * scale
+
+
 def test_learned_filter_lowers_error_against_direct_fbp(gpu_lib):
     """Order-4 coefficients per 8 angle groups plus the residual network, trained on noisy
     phantom linograms against the direct FBP of the same data; measured against the FP64 direct FBP

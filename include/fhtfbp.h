@@ -234,7 +234,9 @@ int fbp_plan_profile_read(fbp_plan_t plan, double* total_ms, int32_t* launches);
  * corrects what the low-order recursive filter leaves.  Convolutions run on the matrix cores
  * with BF16 operands and FP32 accumulation.  Images with one channel are FP32 [b][y][x];
  * 16-channel activations are BF16 NHWC [b][y][x][16] (uint16_t storage).  Supported
- * (cin, cout): (1, 16), (16, 16), (16, 1). */
+ * (cin, cout): (1, 16), (16, 16), (16, 1).  The kernels move BF16 activations, gradients and
+ * packed weights 8 or 16 bytes at a time: such a buffer off a 16-byte boundary gives
+ * FBP_EINVAL before any launch. */
 
 /* Pack FP32 weights w[cout][cin][3][3] into the matrix-core operand order (fbp_cnn_packed_elems
  * (cin) BF16 values; for transpose_flip, fbp_cnn_packed_elems(cout)).  transpose_flip packs the

@@ -88,8 +88,10 @@ def test_cnn_forward_matches_oracle(gpu_lib):
     torch.cuda.synchronize()
     ref = O.residual_cnn(x0.double(), [w["w1"].cpu(), w["w2"].cpu(), w["w3"].cpu()],
                          [w["b1"].cpu(), w["b2"].cpu(), w["b3"].cpu()], bf16_storage=True)
-    # residual part alone (the skip connection would hide errors)
-    assert _rel(got.cpu().double() - x0.double(), ref - x0.double()) < 2e-3
+    # residual part alone (the skip connection would hide errors); the oracle rounds to BF16
+    # where the kernels store, so only FP32 accumulation (and a rare BF16 rounding it flips)
+    # is left: measured 6e-8 to 8e-8
+    assert _rel(got.cpu().double() - x0.double(), ref - x0.double()) < 1e-4
 
 
 def test_cnn_fused_forward_equals_layer_by_layer(gpu_lib):
@@ -127,7 +129,7 @@ def test_cnn_fused_forward_ragged_sizes_match_oracle(gpu_lib, H, W):
     torch.cuda.synchronize()
     ref = O.residual_cnn(x0.double(), [w["w1"].cpu(), w["w2"].cpu(), w["w3"].cpu()],
                          [w["b1"].cpu(), w["b2"].cpu(), w["b3"].cpu()], bf16_storage=True)
-    assert _rel(got.cpu().double() - x0.double(), ref - x0.double()) < 2e-3
+    assert _rel(got.cpu().double() - x0.double(), ref - x0.double()) < 1e-4
 
 
 def test_cnn_backward_matches_oracle(gpu_lib):
@@ -178,6 +180,54 @@ def test_cnn_weight_gradient_matches_fp64(gpu_lib, cin, cout):
     scale = math.sqrt(B * H * W)
     assert float((got[:nw] - gw.reshape(-1)).abs().max()) < 1e-5 * scale
     assert float((got[nw:] - gb).abs().max()) < 1e-5 * scale
+
+
+def _bf16(t):
+    return t.to(torch.float32).to(torch.bfloat16).to(torch.float64)
+
+
+def _cnn_backward_bf16_reference(x0, w, R):
+    """FP64 forward and backward of the residual network with BF16 values exactly where the
+    matrix-core network rounds them: the first layer's input, the weights and the stored hidden
+    activations in the forward pass; the gradients entering each backward convolution
+    (the output gradient as an operand, the stored hidden gradients) in the backward pass.  The
+    weight gradients take the FP32 output gradient and image unrounded, as the library's do."""
+    F = torch.nn.functional
+    x = x0.double()[:, None]
+    wb = {k: _bf16(w[k].cpu()) for k in ("w1", "w2", "w3")}
+    b = {k: w[k].cpu().double() for k in ("b1", "b2", "b3")}
+    h1 = _bf16(torch.relu(F.conv2d(_bf16(x), wb["w1"], b["b1"], padding=1)))
+    h2 = _bf16(torch.relu(F.conv2d(h1, wb["w2"], b["b2"], padding=1)))
+    dout = R.double()[:, None]
+    g3 = torch.nn.grad.conv2d_weight(h2, (1, 16, 3, 3), dout, padding=1)
+    dz2 = _bf16((h2 > 0) * F.conv_transpose2d(_bf16(dout), wb["w3"], padding=1))
+    g2 = torch.nn.grad.conv2d_weight(h1, (16, 16, 3, 3), dz2, padding=1)
+    dz1 = _bf16((h1 > 0) * F.conv_transpose2d(dz2, wb["w2"], padding=1))
+    g1 = torch.nn.grad.conv2d_weight(x, (16, 1, 3, 3), dz1, padding=1)
+    dx = F.conv_transpose2d(dz1, wb["w1"], padding=1) + dout
+    sums = lambda t: t.sum(dim=(0, 2, 3))  # noqa: E731
+    return [dx[:, 0], g1, sums(dz1), g2, sums(dz2), g3, sums(dout)]
+
+
+def test_cnn_backward_matches_bf16_reference(gpu_lib):
+    """The network's backward pass against an FP64 reference that rounds to BF16 at the same
+    points as the kernels: what is left is FP32 accumulation and the rare BF16 rounding that it
+    flips (measured 3e-8 to 1.6e-6 over three seeds), far below the percent-level gap to the
+    unrounded FP64 gradient."""
+    import paper_2007_06289_amd.learned as L
+    N, B = 64, 2
+    x0 = I.phantom_image(I.random_ellipses(N, 8, seed=6, batch=B), N, supersample=2).to(torch.float32)
+    R = torch.randn(B, N, N, generator=torch.Generator().manual_seed(9))
+    w = _cnn_weights(4)
+    params = [w[k].clone().requires_grad_(True) for k in ("w1", "b1", "w2", "b2", "w3", "b3")]
+    xg = x0.cuda().requires_grad_(True)
+    out = L.ResidualCNN.apply(xg, *params)
+    grads = torch.autograd.grad((out * R.cuda()).sum(), [xg] + params)
+    torch.cuda.synchronize()
+    refs = _cnn_backward_bf16_reference(x0, w, R)
+    names = ["x0", "w1", "b1", "w2", "b2", "w3", "b3"]
+    for n, g_, r_ in zip(names, grads, refs):
+        assert _rel(g_.reshape(r_.shape), r_) < 1e-4, n
 
 
 def test_learned_filter_lowers_error_against_direct_fbp(gpu_lib):

@@ -257,8 +257,8 @@ int fbp_cnn_conv(int32_t cin, int32_t cout, const float* in32, const uint16_t* i
 /* The whole network at inference in one launch: out = img + conv3(relu(conv2(relu(conv1(img) +
  * b1)) + b2)) + b3 for FP32 images [batch][h][w] (any h, w >= 1), with w1, w2, w3 packed by
  * fbp_cnn_pack ((1, 16), (16, 16), (16, 1)) and biases b1[16], b2[16], b3[1].  The hidden
- * activations stay on chip (BF16, as fbp_cnn_conv stores them); the result equals the three
- * fbp_cnn_conv calls bit for bit.  out must not overlap img. */
+ * activations stay on chip (BF16, as fbp_cnn_conv stores them); for a finite image the result
+ * equals the three fbp_cnn_conv calls bit for bit.  out must not overlap img. */
 int fbp_cnn_forward(const float* img, const uint16_t* w1, const float* b1, const uint16_t* w2,
                     const float* b2, const uint16_t* w3, const float* b3, float* out,
                     int32_t batch, int32_t h, int32_t w, void* stream);

@@ -406,9 +406,10 @@ __global__ void __launch_bounds__(256) cnn_fused_kernel(const float* __restrict_
     bias2[i] = b2[4 * kg + i];
   }
   const float bias3 = b3[0];
-  // layer 1: lane group kg < 3 reads row kg of the 3 x 3 window, group 3 contributes zeros
+  // layer 1: lane group kg < 3 reads row kg of the 3 x 3 window; group 3 reads row 2 again,
+  // which adds nothing: its packed weights (and every fourth one) are zero, and the x region
+  // holds finite values
   const int x_row = min(kg, 2) * T::XC;
-  const uint32_t x_keep = kg < 3 ? 0xffffffffu : 0u;
   // The weights and biases are waited for here, before the tile loop: an empty asm that reads
   // them makes the compiler complete their loads once, so that inside the loop no wait for
   // them also waits for the next tile's x loads, which are issued later.
@@ -471,13 +472,13 @@ __global__ void __launch_bounds__(256) cnn_fused_kernel(const float* __restrict_
       *reinterpret_cast<uint2*>(dst + ((kg >> 1) * px_total + px) * 8 + (kg & 1) * 4) = w;
     };
 
-    // layer 1: x (1 channel) -> h1 (16), one 16x16x16 step per group: lane group kg < 3 holds
-    // the three taps of window row kg (converted in pairs) and a zero
+    // layer 1: x (1 channel) -> h1 (16), one 16x16x16 step per group: lane group kg holds the
+    // three taps of window row min(kg, 2) (converted in pairs) and a zero
     auto a1 = [&](int p) -> bf16x4 {
       const int r = p / T::H1C, c = p - r * T::H1C;
       const float* xp = sxc + r * T::XC + c + x_row;
-      const uint32_t w0 = pack2_bf16(xp[0], xp[1]) & x_keep;
-      const uint32_t w1 = pack2_bf16(xp[2], 0.f) & x_keep;
+      const uint32_t w0 = pack2_bf16(xp[0], xp[1]);
+      const uint32_t w1 = pack2_bf16(xp[2], 0.f);
       return __builtin_bit_cast(bf16x4, make_uint2(w0, w1));
     };
     // two groups (g, g + 4) at a time, as in the layers below
@@ -504,6 +505,9 @@ __global__ void __launch_bounds__(256) cnn_fused_kernel(const float* __restrict_
       const Ops16 oa = load_ops16<T::H1C, T::H1Px>(sh1, ra * T::H1C + ca, kg);
       const Ops16 ob = load_ops16<T::H1C, T::H1Px>(sh1, rb * T::H1C + cb, kg);
       f32x4 acca = {0.f, 0.f, 0.f, 0.f}, accb = {0.f, 0.f, 0.f, 0.f};
+      // the wave's priority is raised while it issues its chain, so that the matrix core is
+      // fed while the block's other waves load
+      __builtin_amdgcn_s_setprio(1);
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         acca = mfma32(w2op[s], oa.a[s], acca);
@@ -511,6 +515,7 @@ __global__ void __launch_bounds__(256) cnn_fused_kernel(const float* __restrict_
       }
       acca = mfma16(w2op4, oa.a4, acca);
       accb = mfma16(w2op4, ob.a4, accb);
+      __builtin_amdgcn_s_setprio(0);
       store4(sh2, T::H2Store, acca, bias2, pa, T::H2C, -1, -1);
       store4(sh2, T::H2Store, accb, bias2, pb, T::H2C, -1, -1);
     }
@@ -526,6 +531,7 @@ __global__ void __launch_bounds__(256) cnn_fused_kernel(const float* __restrict_
       const Ops16 oa = load_ops16<T::H2C, T::H2Store>(sh2, ra * T::H2C + ca, kg);
       const Ops16 ob = load_ops16<T::H2C, T::H2Store>(sh2, rb * T::H2C + cb, kg);
       f32x4 acca = {0.f, 0.f, 0.f, 0.f}, accb = {0.f, 0.f, 0.f, 0.f};
+      __builtin_amdgcn_s_setprio(1);
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         acca = mfma32(w3op[s], oa.a[s], acca);
@@ -533,6 +539,7 @@ __global__ void __launch_bounds__(256) cnn_fused_kernel(const float* __restrict_
       }
       acca = mfma16(w3op4, oa.a4, acca);
       accb = mfma16(w3op4, ob.a4, accb);
+      __builtin_amdgcn_s_setprio(0);
       if (kg == 0) {
         const int gya = Y0 + ra, gxa = X0 + ca, gyb = Y0 + rb, gxb = X0 + cb;
         if (gya < H && gxa < W)

@@ -19,6 +19,11 @@
 //     step 3); then one 16x16x16 step for tap 8, lane group g holding channels 4 g .. + 3.
 //   1 input channel: one 16x16x16 step, lane group g < 3 holding taps 3 g .. 3 g + 2 (row dy =
 //     g) and a zero, group 3 zeros.
+// A convolution from 16 channels to one turns the roles around: one 16x16x16 step per pixel
+// group with the taps as the rows of A (A[t][c] = w[c][t], rows 9..15 zero) and the pixel's
+// channels as B (lane group g: channels 4 g .. + 3, the layout a 16-channel layer's result
+// already has) gives the nine per-tap partial sums of each pixel; an output pixel is then the
+// sum of its nine neighbours' partials in tap order, in FP32.
 // BF16 rounding is the hardware's round-to-nearest-even conversion.  The backward convolution
 // with respect to the input is the same kernel with the weights transposed and the taps
 // flipped (packed by cnn_pack_kernel), and its output multiplied by the ReLU mask of the layer
@@ -85,7 +90,15 @@ __global__ void cnn_pack_kernel(const float* __restrict__ w, uint16_t* __restric
   const int co_n = transpose_flip ? cin : cout;    // its output channels
   const int step = e >> 9, r = e & 511;
   int tap = -1, c = 0, n = 0;
-  if (ci_n == 1 || step == 4) {          // 16x16x16 step: lane r / 4 holds K 4 (lane / 16) + j
+  if (ci_n == 16 && co_n == 1) {         // taps x channels: A[t][c] at lane t + 16 (c / 4), c % 4
+    if (step == 0 && r < 256) {
+      const int lane = r >> 2, t = lane & 15;
+      if (t < 9) {
+        tap = t;
+        c = 4 * (lane >> 4) + (r & 3);
+      }
+    }
+  } else if (ci_n == 1 || step == 4) {   // 16x16x16 step: lane r / 4 holds K 4 (lane / 16) + j
     if (r < 256) {
       const int lane = r >> 2, j = r & 3, g = lane >> 4;
       n = lane & 15;
@@ -112,7 +125,8 @@ __global__ void cnn_pack_kernel(const float* __restrict__ w, uint16_t* __restric
 
 // CIN in {1, 16} input channels (FP32 image if 1, BF16 NHWC if 16); COUT in {1, 16}.
 // COUT == 16: out16 (BF16 NHWC) = [relu]((acc + bias) [* (mask > 0)]).
-// COUT == 1: out32 (FP32) = acc + bias [+ resid].
+// COUT == 1: out32 (FP32) = acc + bias [+ resid]; from 16 channels, acc is the sum in tap order
+// of the per-tap partials of the pixel's nine neighbours (the K order of the header).
 template <int CIN, int COUT>
 __global__ void __launch_bounds__(256) cnn_conv_kernel(const float* __restrict__ in32,
                                                        const uint16_t* __restrict__ in16,
@@ -134,6 +148,46 @@ __global__ void __launch_bounds__(256) cnn_conv_kernel(const float* __restrict__
   const int m = lane & 15, kg = lane >> 4;
   const int x = (xg << 4) + m;
   auto inside = [&](int yy, int xx) { return yy >= 0 && yy < H && xx >= 0 && xx < W; };
+  if constexpr (CIN == 16 && COUT == 1) {
+    // The group's outputs (y, x), x = 16 xg + m, read the partials of rows y - 1 .. y + 1 at
+    // neighbourhood columns 0 .. 17 (image columns 16 xg - 1 .. 16 xg + 16): per row one
+    // 16x16x16 step for columns 0 .. 15 and one for 16, 17 (lanes m < 2).  The wave keeps them
+    // in its own LDS area [tap][row][column].
+    __shared__ float spart[4][9 * 3 * 32];
+    float* sp = spart[threadIdx.x >> 6];
+    const bf16x4 at = reinterpret_cast<const bf16x4*>(wop)[lane];
+#pragma unroll
+    for (int rr = 0; rr < 3; ++rr) {
+      const int yy = y + rr - 1;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int col = 16 * h + m;
+        const int xx = (xg << 4) - 1 + col;
+        const bool use = h == 0 || m < 2;
+        bf16x4 bv = bf16x4{0, 0, 0, 0};
+        if (use && inside(yy, xx))
+          bv = *reinterpret_cast<const bf16x4*>(in16 + (((size_t)b * H + yy) * W + xx) * 16 +
+                                                4 * kg);
+        const f32x4 pt = mfma16(at, bv, f32x4{0.f, 0.f, 0.f, 0.f});
+        if (use) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (4 * kg + i < 9) sp[((4 * kg + i) * 3 + rr) * 32 + col] = pt[i];
+        }
+      }
+    }
+    // the wave's partials are in LDS before any lane reads them
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    if (kg == 0) {
+      const float* q = sp + m;
+      float sum = q[0];
+#pragma unroll
+      for (int t = 1; t < 9; ++t) sum += q[(t * 3 + t / 3) * 32 + t % 3];
+      const size_t pix = ((size_t)b * H + y) * W + x;
+      out32[pix] = sum + (bias ? bias[0] : 0.f) + (resid ? resid[pix] : 0.f);
+    }
+    return;
+  }
   f32x4 acc = {0.f, 0.f, 0.f, 0.f};
   if constexpr (CIN == 16) {
 #pragma unroll
@@ -325,11 +379,12 @@ __global__ void __launch_bounds__(256) cnn_reduce_kernel(const float* __restrict
 // out = x + conv3(relu(conv2(relu(conv1(x) + b1)) + b2)) + b3 over tiles of TH x TW output
 // pixels.  A block loads the x region the tile depends on (three pixels of halo on each
 // side, zero outside the image) into LDS, computes h1 over the tile plus two pixels of halo
-// and h2 over the tile plus one, both BF16 in LDS (zero outside the image: the zero padding
-// of the next layer), and writes the tile.  Each layer issues the same matrix-core operations
-// with the same operands as cnn_conv_kernel (same K order, same BF16 roundings, bias then
-// ReLU, then the residual), so the image equals the three separate launches bit for bit;
-// only h1 and h2 never go to HBM.  A group is 16 consecutive pixels of a region in row-major
+// (BF16 in LDS, zero outside the image: the zero padding of the next layer) and h2 over the
+// tile plus one, whose per-tap partials for layer 3 go to LDS instead of h2 itself, and writes
+// the tile.  Each layer issues the same matrix-core operations with the same operands as
+// cnn_conv_kernel (same K order, same BF16 roundings, bias then ReLU, the partials summed in
+// the same order, then the residual), so the image equals the three separate launches bit for
+// bit; only h1 and h2 never go to HBM.  A group is 16 consecutive pixels of a region in row-major
 // order; lane (m, kg) of a wave ends with channels 4 kg .. + 3 of pixel m.  In LDS the 16
 // channels of a pixel are split in two planes of 8 (16 bytes per pixel and plane): the 16
 // lanes that read one operand part then read consecutive words.  With the K order of the
@@ -342,11 +397,11 @@ struct FusedTile {
   static constexpr int H2R = TH + 2, H2C = TW + 2;       // h2 region
   static constexpr int H1Px = H1R * H1C, H2Px = H2R * H2C;
   static constexpr int H1Groups = H1Px / 16, H2Groups = (H2Px + 15) / 16;
-  // h2 is stored for whole groups of 16 pixels (the last group's extra pixels are never read)
+  // h2's partials are stored for whole groups of 16 pixels (the last group's extra pixels
+  // are never read)
   static constexpr int H2Store = H2Groups * 16;
-  static constexpr int OutGroups = TH * (TW / 16);
   static_assert(H1Px % 16 == 0, "h1 region in whole groups of 16 pixels");
-  static_assert(TW % 16 == 0 && OutGroups % 8 == 0, "output groups pair up");
+  static_assert((TH * TW) % 256 == 0, "output pixels in whole passes of the block");
 };
 
 // A 16-channel layer's operands for the group whose lane m has base pixel q (top-left of its
@@ -386,19 +441,16 @@ __global__ void __launch_bounds__(256) cnn_fused_kernel(const float* __restrict_
   constexpr int XPT = (XPX + 255) / 256;             // x values per thread and tile
   __shared__ float sx[2][XPX];                       // this tile's x region and the next one's
   __shared__ __align__(16) uint16_t sh1[2 * T::H1Px * 8];
-  __shared__ __align__(16) uint16_t sh2[2 * T::H2Store * 8];
+  __shared__ float sp3[9 * T::H2Store];              // layer 3's per-tap partials of h2
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int m = lane & 15, kg = lane >> 4;
   const bf16x4 w1op = reinterpret_cast<const bf16x4*>(w1)[lane];
-  bf16x8 w2op[4], w3op[4];
+  bf16x8 w2op[4];
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    w2op[s] = w2[s * 64 + lane];
-    w3op[s] = w3[s * 64 + lane];
-  }
+  for (int s = 0; s < 4; ++s) w2op[s] = w2[s * 64 + lane];
   const bf16x4 w2op4 = reinterpret_cast<const bf16x4*>(w2 + 4 * 64)[lane];
-  const bf16x4 w3op4 = reinterpret_cast<const bf16x4*>(w3 + 4 * 64)[lane];
+  const bf16x4 w3t = reinterpret_cast<const bf16x4*>(w3)[lane];   // taps x channels
   float bias1[4], bias2[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -415,7 +467,7 @@ __global__ void __launch_bounds__(256) cnn_fused_kernel(const float* __restrict_
   // them also waits for the next tile's x loads, which are issued later.
   asm volatile("" ::"v"(w1op), "v"(w2op[0]), "v"(w2op[1]), "v"(w2op[2]), "v"(w2op[3]),
                "v"(w2op4));
-  asm volatile("" ::"v"(w3op[0]), "v"(w3op[1]), "v"(w3op[2]), "v"(w3op[3]), "v"(w3op4));
+  asm volatile("" ::"v"(w3t));
   asm volatile("" ::"v"(bias1[0]), "v"(bias1[1]), "v"(bias1[2]), "v"(bias1[3]), "v"(bias2[0]),
                "v"(bias2[1]), "v"(bias2[2]), "v"(bias2[3]), "v"(bias3));
 
@@ -457,10 +509,9 @@ __global__ void __launch_bounds__(256) cnn_fused_kernel(const float* __restrict_
     // every region pixel of an interior tile lies in the image: no zeroing to decide
     const bool interior = Y0 >= 3 && X0 >= 3 && Y0 + TH + 3 <= H && X0 + TW + 3 <= W;
 
-    // Bias, BF16, ReLU of a lane's four channels of region pixel px (zero outside the image),
-    // stored as one 8-byte word into plane kg / 2 of a region of `px_total` pixels.
-    auto store4 = [&](uint16_t* dst, int px_total, const f32x4& acc, const float* bias, int px,
-                      int cols, int oy, int ox) {
+    // Bias, BF16, ReLU of a lane's four channels of region pixel px (zero outside the image).
+    auto hword = [&](const f32x4& acc, const float* bias, int px, int cols, int oy,
+                     int ox) -> uint2 {
       uint2 w = pack4_bf16(acc[0] + bias[0], acc[1] + bias[1], acc[2] + bias[2],
                            acc[3] + bias[3]);
       w = make_uint2(relu_bf16x2(w.x), relu_bf16x2(w.y));
@@ -469,7 +520,22 @@ __global__ void __launch_bounds__(256) cnn_fused_kernel(const float* __restrict_
         const int gy = Y0 + oy + rr, gx = X0 + ox + cc;
         if (!(gy >= 0 && gy < H && gx >= 0 && gx < W)) w = make_uint2(0u, 0u);
       }
+      return w;
+    };
+    // ... stored as one 8-byte word into plane kg / 2 of a region of `px_total` pixels
+    auto store4 = [&](uint16_t* dst, int px_total, const f32x4& acc, const float* bias, int px,
+                      int cols, int oy, int ox) {
+      const uint2 w = hword(acc, bias, px, cols, oy, ox);
       *reinterpret_cast<uint2*>(dst + ((kg >> 1) * px_total + px) * 8 + (kg & 1) * 4) = w;
+    };
+    // h2 of pixel px is layer 3's B operand as it stands (lane group kg: channels 4 kg .. + 3):
+    // one 16x16x16 step against the taps gives its nine per-tap partials, kept in LDS
+    auto partials3 = [&](const f32x4& acc, int px) {
+      const uint2 w = hword(acc, bias2, px, T::H2C, -1, -1);
+      const f32x4 pt = mfma16(w3t, __builtin_bit_cast(bf16x4, w), f32x4{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (4 * kg + i < 9) sp3[(4 * kg + i) * T::H2Store + px] = pt[i];
     };
 
     // layer 1: x (1 channel) -> h1 (16), one 16x16x16 step per group: lane group kg holds the
@@ -481,7 +547,7 @@ __global__ void __launch_bounds__(256) cnn_fused_kernel(const float* __restrict_
       const uint32_t w1 = pack2_bf16(xp[2], 0.f);
       return __builtin_bit_cast(bf16x4, make_uint2(w0, w1));
     };
-    // two groups (g, g + 4) at a time, as in the layers below
+    // two groups (g, g + 4) at a time, as in layer 2
     for (int g = wave; g < T::H1Groups; g += 8) {
       const int gb = g + 4 < T::H1Groups ? g + 4 : g;
       const int pa = g * 16 + m, pb = gb * 16 + m;
@@ -492,7 +558,7 @@ __global__ void __launch_bounds__(256) cnn_fused_kernel(const float* __restrict_
       store4(sh1, T::H1Px, acca, bias1, pa, T::H1C, -2, -2);
       store4(sh1, T::H1Px, accb, bias1, pb, T::H1C, -2, -2);
     }
-    __syncthreads();   // h1 complete; the previous tile's layer 3 is done with h2
+    __syncthreads();   // h1 complete; the previous tile's layer 3 is done with the partials
 
     // layer 2: h1 (16) -> h2 (16).  A wave takes two groups at a time (its groups g and g + 4;
     // the second repeats the first when there is none): their operands load together and the
@@ -516,44 +582,32 @@ __global__ void __launch_bounds__(256) cnn_fused_kernel(const float* __restrict_
       acca = mfma16(w2op4, oa.a4, acca);
       accb = mfma16(w2op4, ob.a4, accb);
       __builtin_amdgcn_s_setprio(0);
-      store4(sh2, T::H2Store, acca, bias2, pa, T::H2C, -1, -1);
-      store4(sh2, T::H2Store, accb, bias2, pb, T::H2C, -1, -1);
+      partials3(acca, pa);
+      partials3(accb, pb);
     }
     if (tn < total_tiles) store_x(sx[buf ^ 1]);
-    __syncthreads();   // h2 and the next tile's x region complete
+    __syncthreads();   // the partials and the next tile's x region complete
 
-    // layer 3: h2 (16) -> 1 channel (channel 0: lanes kg = 0, first element), plus bias and
-    // the residual; a group is 16 pixels of a tile row, two groups (g, g + 4) per wave at a time
+    // layer 3: each output pixel sums the partials of its nine h2 neighbours in tap order,
+    // then adds the bias and the residual (two pixels per thread, a row of 32 per half wave)
     float* dst = out + (size_t)b * H * W;
-    for (int g = wave; g < T::OutGroups; g += 8) {
-      const int ra = g / (TW / 16), ca = (g % (TW / 16)) * 16 + m;
-      const int rb = (g + 4) / (TW / 16), cb = ((g + 4) % (TW / 16)) * 16 + m;
-      const Ops16 oa = load_ops16<T::H2C, T::H2Store>(sh2, ra * T::H2C + ca, kg);
-      const Ops16 ob = load_ops16<T::H2C, T::H2Store>(sh2, rb * T::H2C + cb, kg);
-      f32x4 acca = {0.f, 0.f, 0.f, 0.f}, accb = {0.f, 0.f, 0.f, 0.f};
-      __builtin_amdgcn_s_setprio(1);
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        acca = mfma32(w3op[s], oa.a[s], acca);
-        accb = mfma32(w3op[s], ob.a[s], accb);
-      }
-      acca = mfma16(w3op4, oa.a4, acca);
-      accb = mfma16(w3op4, ob.a4, accb);
-      __builtin_amdgcn_s_setprio(0);
-      if (kg == 0) {
-        const int gya = Y0 + ra, gxa = X0 + ca, gyb = Y0 + rb, gxb = X0 + cb;
-        if (gya < H && gxa < W)
-          dst[(size_t)gya * W + gxa] = acca[0] + bias3 + sxc[(ra + 3) * T::XC + ca + 3];
-        if (gyb < H && gxb < W)
-          dst[(size_t)gyb * W + gxb] = accb[0] + bias3 + sxc[(rb + 3) * T::XC + cb + 3];
-      }
+    for (int k = 0; k < TH * TW / 256; ++k) {
+      const int e = tid + 256 * k;
+      const int r = e / TW, c = e - r * TW;
+      const float* q = sp3 + r * T::H2C + c;
+      float sum = q[0];
+#pragma unroll
+      for (int t = 1; t < 9; ++t) sum += q[t * T::H2Store + (t / 3) * T::H2C + t % 3];
+      const int gy = Y0 + r, gx = X0 + c;
+      if (gy < H && gx < W) dst[(size_t)gy * W + gx] = sum + bias3 + sxc[(r + 3) * T::XC + c + 3];
     }
   }
 }
 
 }  // namespace
 
-// Output tile of the fused network: 16 x 32 pixels (50 KB of LDS per block).  The launch is
+// Output tile of the fused network: 16 x 32 pixels (51 KB of LDS per block, three per CU).  The launch is
 // persistent: as many blocks as the device holds at once, each looping over tiles.
 constexpr int kFuseTH = 16, kFuseTW = 32;
 

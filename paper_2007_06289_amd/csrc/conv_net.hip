@@ -442,6 +442,7 @@ __global__ void __launch_bounds__(256) cnn_fused_kernel(const float* __restrict_
   __shared__ float sx[2][XPX];                       // this tile's x region and the next one's
   __shared__ __align__(16) uint16_t sh1[2 * T::H1Px * 8];
   __shared__ float sp3[9 * T::H2Store];              // layer 3's per-tap partials of h2
+  __shared__ float sdrop[256];                       // where lanes without a tap write
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int m = lane & 15, kg = lane >> 4;
@@ -533,9 +534,13 @@ __global__ void __launch_bounds__(256) cnn_fused_kernel(const float* __restrict_
     auto partials3 = [&](const f32x4& acc, int px) {
       const uint2 w = hword(acc, bias2, px, T::H2C, -1, -1);
       const f32x4 pt = mfma16(w3t, __builtin_bit_cast(bf16x4, w), f32x4{0.f, 0.f, 0.f, 0.f});
+      // rows 9 .. 15 hold no tap: their lanes write into a slot of their own instead of
+      // branching around the store
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-        if (4 * kg + i < 9) sp3[(4 * kg + i) * T::H2Store + px] = pt[i];
+      for (int i = 0; i < 4; ++i) {
+        float* d = 4 * kg + i < 9 ? &sp3[(4 * kg + i) * T::H2Store + px] : &sdrop[tid];
+        *d = pt[i];
+      }
     };
 
     // layer 1: x (1 channel) -> h1 (16), one 16x16x16 step per group: lane group kg holds the
@@ -607,7 +612,7 @@ __global__ void __launch_bounds__(256) cnn_fused_kernel(const float* __restrict_
 
 }  // namespace
 
-// Output tile of the fused network: 16 x 32 pixels (51 KB of LDS per block, three per CU).  The launch is
+// Output tile of the fused network: 16 x 32 pixels (52 KB of LDS per block, three per CU).  The launch is
 // persistent: as many blocks as the device holds at once, each looping over tiles.
 constexpr int kFuseTH = 16, kFuseTW = 32;
 

@@ -65,6 +65,20 @@ class ResidualCNN(torch.autograd.Function):
                 g2[n2:], g3[:n3].view(1, HIDDEN, 3, 3), g3[n3:])
 
 
+def pack_cnn(w: dict) -> dict:
+    """The network's weights packed once for inference (``residual_cnn_packed``)."""
+    return {"p1": api.fbp_cnn_pack(w["w1"].detach()), "p2": api.fbp_cnn_pack(w["w2"].detach()),
+            "p3": api.fbp_cnn_pack(w["w3"].detach()), "b1": w["b1"].detach(),
+            "b2": w["b2"].detach(), "b3": w["b3"].detach()}
+
+
+def residual_cnn_packed(x0: torch.Tensor, pk: dict, out: torch.Tensor | None = None):
+    """The network at inference in one fused launch, on weights packed by ``pack_cnn``; the
+    same result as ``residual_cnn`` bit for bit."""
+    return api.fbp_cnn_forward(x0.contiguous(), pk["p1"], pk["b1"], pk["p2"], pk["b2"],
+                               pk["p3"], pk["b3"], out)
+
+
 def residual_cnn(x0: torch.Tensor, w: dict) -> torch.Tensor:
     """The network on [B, H, W] images.  When no gradient is needed, one fused launch
     (``fbp_cnn_forward``: hidden activations stay on chip, same result bit for bit); otherwise

@@ -113,6 +113,10 @@ def test_cnn_fused_forward_equals_layer_by_layer(gpu_lib):
     assert torch.equal(fused, layers)
     with torch.no_grad():
         assert torch.equal(L.residual_cnn(x0, w), fused)
+    # inference on weights packed once, into a given output
+    out = torch.empty_like(x0)
+    assert L.residual_cnn_packed(x0, L.pack_cnn(w), out) is out
+    assert torch.equal(out, fused)
 
 
 @pytest.mark.parametrize("H,W", [(100, 72), (17, 33), (1, 5)])

@@ -11,12 +11,11 @@
 // lane l holds A[l % 16][8 (l / 16) .. + 7] and B[8 (l / 16) .. + 7][l % 16]; in a 16x16x16 step
 // A[l % 16][4 (l / 16) .. + 3] and B[4 (l / 16) .. + 3][l % 16].
 //
-// K order (taps t = 3 dy + dx, dy, dx in 0..2 for the offsets -1..1), chosen so that each lane's
-// reads are one base per step kind plus immediate offsets, with no padding taps:
-//   16 input channels: four 16x16x32 steps s = 0..3, lane group g = l / 16 holding tap
-//     (g < 2 ? kTapA : kTapB)[s] and channels 8 (g % 2) .. + 7, where kTapA = {0, 1, 2, 6} and
-//     kTapB = {3, 4, 5, 7} (tap B is tap A one row down in steps 0..2, one column right in
-//     step 3); then one 16x16x16 step for tap 8, lane group g holding channels 4 g .. + 3.
+// K order (taps t = 3 dy + dx, dy, dx in 0..2 for the offsets -1..1), chosen so that the
+// operands of one window row serve every output row that uses it, with no padding taps:
+//   16 input channels: three 16x16x32 steps s = 0..2 for window row dy = s, lane group g
+//     holding column dx = g / 2 and channels 8 (g % 2) .. + 7; then three 16x16x16 steps for
+//     column dx = 2 of rows dy = 0..2, lane group g holding channels 4 g .. + 3.
 //   1 input channel: one 16x16x16 step, lane group g < 3 holding taps 3 g .. 3 g + 2 (row dy =
 //     g) and a zero, group 3 zeros.
 // A convolution from 16 channels to one turns the roles around: one 16x16x16 step per pixel
@@ -65,10 +64,6 @@ __device__ __forceinline__ uint32_t relu_bf16x2(uint32_t w) {
                             __builtin_elementwise_max(__builtin_bit_cast(short2v, w), short2v{0, 0}));
 }
 
-// Taps of the two lane-group halves in the four 16x16x32 steps of a 16-channel input (tap B is
-// tap A one row down in steps 0..2, one column right in step 3); tap 8 follows in a 16x16x16 step.
-__device__ constexpr int kTapA[4] = {0, 1, 2, 6};
-__device__ constexpr int kTapB[4] = {3, 4, 5, 7};
 
 __device__ __forceinline__ f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
@@ -98,22 +93,22 @@ __global__ void cnn_pack_kernel(const float* __restrict__ w, uint16_t* __restric
         c = 4 * (lane >> 4) + (r & 3);
       }
     }
-  } else if (ci_n == 1 || step == 4) {   // 16x16x16 step: lane r / 4 holds K 4 (lane / 16) + j
-    if (r < 256) {
-      const int lane = r >> 2, j = r & 3, g = lane >> 4;
+  } else if (ci_n == 16) {               // 16 -> 16: the 16x16x32 steps, then the 16x16x16 ones
+    if (e < 3 * 512) {                   // row dy = step, lane l: column (l / 16) / 2
+      const int lane = r >> 3, j = r & 7, g = lane >> 4;
       n = lane & 15;
-      if (ci_n == 1) {
-        if (g < 3 && j < 3) tap = 3 * g + j;
-      } else {
-        tap = 8;
-        c = 4 * g + j;
-      }
+      tap = 3 * step + (g >> 1);
+      c = (g & 1) * 8 + j;
+    } else if (e < 3 * 512 + 3 * 256) {  // row dy = (e - 1536) / 256, column 2
+      const int r4 = e - 3 * 512, lane = (r4 & 255) >> 2, j = r4 & 3, g = lane >> 4;
+      n = lane & 15;
+      tap = 3 * (r4 >> 8) + 2;
+      c = 4 * g + j;
     }
-  } else {                               // 16x16x32 step s < 4
-    const int lane = r >> 3, j = r & 7, g = lane >> 4;
+  } else if (r < 256) {                  // 1 input channel: one 16x16x16 step
+    const int lane = r >> 2, j = r & 3, g = lane >> 4;
     n = lane & 15;
-    tap = g < 2 ? kTapA[step] : kTapB[step];
-    c = (g & 1) * 8 + j;
+    if (g < 3 && j < 3) tap = 3 * g + j;
   }
   float v = 0.f;
   if (tap >= 0 && n < co_n && c < ci_n) {
@@ -190,21 +185,26 @@ __global__ void __launch_bounds__(256) cnn_conv_kernel(const float* __restrict__
   }
   f32x4 acc = {0.f, 0.f, 0.f, 0.f};
   if constexpr (CIN == 16) {
+    // window rows dy = 0..2 at columns dx = kg / 2 (16x16x32), then column 2 (16x16x16)
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int tap = kg < 2 ? kTapA[s] : kTapB[s];
-      const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
+    for (int s = 0; s < 3; ++s) {
+      const int yy = y + s - 1, xx = x + (kg >> 1) - 1;
       bf16x8 a = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
       if (inside(yy, xx))
         a = *reinterpret_cast<const bf16x8*>(in16 + (((size_t)b * H + yy) * W + xx) * 16 +
                                              (kg & 1) * 8);
       acc = mfma32(wop[s * 64 + lane], a, acc);
     }
-    bf16x4 a = bf16x4{0, 0, 0, 0};
-    if (inside(y + 1, x + 1))
-      a = *reinterpret_cast<const bf16x4*>(in16 + (((size_t)b * H + y + 1) * W + x + 1) * 16 +
-                                           4 * kg);
-    acc = mfma16(reinterpret_cast<const bf16x4*>(wop + 4 * 64)[lane], a, acc);
+    asm volatile("s_nop 7\n\ts_nop 7" : "+v"(acc));   // as in the fused kernel's layer 2
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      const int yy = y + s - 1, xx = x + 1;
+      bf16x4 a = bf16x4{0, 0, 0, 0};
+      if (inside(yy, xx))
+        a = *reinterpret_cast<const bf16x4*>(in16 + (((size_t)b * H + yy) * W + xx) * 16 +
+                                             4 * kg);
+      acc = mfma16(reinterpret_cast<const bf16x4*>(wop)[3 * 128 + s * 64 + lane], a, acc);
+    }
   } else {
     bf16x4 a;
 #pragma unroll
@@ -384,46 +384,24 @@ __global__ void __launch_bounds__(256) cnn_reduce_kernel(const float* __restrict
 // the tile.  Each layer issues the same matrix-core operations with the same operands as
 // cnn_conv_kernel (same K order, same BF16 roundings, bias then ReLU, the partials summed in
 // the same order, then the residual), so the image equals the three separate launches bit for
-// bit; only h1 and h2 never go to HBM.  A group is 16 consecutive pixels of a region in row-major
-// order; lane (m, kg) of a wave ends with channels 4 kg .. + 3 of pixel m.  In LDS the 16
-// channels of a pixel are split in two planes of 8 (16 bytes per pixel and plane): the 16
-// lanes that read one operand part then read consecutive words.  With the K order of the
-// header, a lane's operand reads for one group are three per-lane bases plus immediate
-// offsets.
+// bit; only h1 and h2 never go to HBM.  A group is 16 pixels (layer 1: consecutive in the
+// region's row-major order; layer 2: 16 columns of one row); lane (m, kg) of a wave ends with
+// channels 4 kg .. + 3 of pixel m.  In LDS the 16 channels of a pixel are split in two planes
+// of 8 (16 bytes per pixel and plane): the 16 lanes that read one operand part then read
+// consecutive words.  The tile is 30 columns wide so that h2's rows are 32: two segments of
+// 16 columns, down which layer 2's waves walk (the header's K order makes one window row's
+// operands serve the three output rows that use it).
 template <int TH, int TW>
 struct FusedTile {
   static constexpr int XR = TH + 6, XC = TW + 6;         // x region
   static constexpr int H1R = TH + 4, H1C = TW + 4;       // h1 region
   static constexpr int H2R = TH + 2, H2C = TW + 2;       // h2 region
   static constexpr int H1Px = H1R * H1C, H2Px = H2R * H2C;
-  static constexpr int H1Groups = H1Px / 16, H2Groups = (H2Px + 15) / 16;
-  // h2's partials are stored for whole groups of 16 pixels (the last group's extra pixels
-  // are never read)
-  static constexpr int H2Store = H2Groups * 16;
-  static_assert(H1Px % 16 == 0, "h1 region in whole groups of 16 pixels");
-  static_assert((TH * TW) % 256 == 0, "output pixels in whole passes of the block");
+  // h1 is computed in whole groups of 16 pixels (the last group's extra pixels are never read)
+  static constexpr int H1Groups = (H1Px + 15) / 16, H1Store = H1Groups * 16;
+  static constexpr int H2Store = H2Px;
+  static_assert(H2C == 32 && H2R % 2 == 0, "h2 rows of two 16-column segments, rows split in two");
 };
-
-// A 16-channel layer's operands for the group whose lane m has base pixel q (top-left of its
-// 3 x 3 window) in a region of `cols` columns and planes of `plane` pixels: steps 0..2 read
-// row (kg / 2) at columns 0..2, step 3 row 2 at column kg / 2, the 16x16x16 step pixel (2, 2).
-struct Ops16 {
-  bf16x8 a[4];
-  bf16x4 a4;
-};
-template <int COLS, int PLANE>
-__device__ __forceinline__ Ops16 load_ops16(const uint16_t* src, int q, int kg) {
-  const uint16_t* p = src + q * 8;
-  const uint16_t* pa = p + ((kg & 1) * PLANE + (kg >> 1) * COLS) * 8;
-  const uint16_t* pb = p + ((kg & 1) * PLANE + 2 * COLS + (kg >> 1)) * 8;
-  const uint16_t* pc = p + ((kg >> 1) * PLANE + 2 * COLS + 2) * 8 + (kg & 1) * 4;
-  Ops16 o;
-#pragma unroll
-  for (int s = 0; s < 3; ++s) o.a[s] = *reinterpret_cast<const bf16x8*>(pa + s * 8);
-  o.a[3] = *reinterpret_cast<const bf16x8*>(pb);
-  o.a4 = *reinterpret_cast<const bf16x4*>(pc);
-  return o;
-}
 
 template <int TH, int TW>
 __global__ void __launch_bounds__(256) cnn_fused_kernel(const float* __restrict__ in,
@@ -440,17 +418,20 @@ __global__ void __launch_bounds__(256) cnn_fused_kernel(const float* __restrict_
   constexpr int XPX = T::XR * T::XC;
   constexpr int XPT = (XPX + 255) / 256;             // x values per thread and tile
   __shared__ float sx[2][XPX];                       // this tile's x region and the next one's
-  __shared__ __align__(16) uint16_t sh1[2 * T::H1Px * 8];
+  __shared__ __align__(16) uint16_t sh1[2 * T::H1Store * 8];
   __shared__ float sp3[9 * T::H2Store];              // layer 3's per-tap partials of h2
   __shared__ float sdrop[256];                       // where lanes without a tap write
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int m = lane & 15, kg = lane >> 4;
   const bf16x4 w1op = reinterpret_cast<const bf16x4*>(w1)[lane];
-  bf16x8 w2op[4];
+  bf16x8 w2r[3];
+  bf16x4 w2d[3];
 #pragma unroll
-  for (int s = 0; s < 4; ++s) w2op[s] = w2[s * 64 + lane];
-  const bf16x4 w2op4 = reinterpret_cast<const bf16x4*>(w2 + 4 * 64)[lane];
+  for (int s = 0; s < 3; ++s) {
+    w2r[s] = w2[s * 64 + lane];
+    w2d[s] = reinterpret_cast<const bf16x4*>(w2)[3 * 128 + s * 64 + lane];
+  }
   const bf16x4 w3t = reinterpret_cast<const bf16x4*>(w3)[lane];   // taps x channels
   float bias1[4], bias2[4];
 #pragma unroll
@@ -466,8 +447,8 @@ __global__ void __launch_bounds__(256) cnn_fused_kernel(const float* __restrict_
   // The weights and biases are waited for here, before the tile loop: an empty asm that reads
   // them makes the compiler complete their loads once, so that inside the loop no wait for
   // them also waits for the next tile's x loads, which are issued later.
-  asm volatile("" ::"v"(w1op), "v"(w2op[0]), "v"(w2op[1]), "v"(w2op[2]), "v"(w2op[3]),
-               "v"(w2op4));
+  asm volatile("" ::"v"(w1op), "v"(w2r[0]), "v"(w2r[1]), "v"(w2r[2]), "v"(w2d[0]), "v"(w2d[1]),
+               "v"(w2d[2]));
   asm volatile("" ::"v"(w3t));
   asm volatile("" ::"v"(bias1[0]), "v"(bias1[1]), "v"(bias1[2]), "v"(bias1[3]), "v"(bias2[0]),
                "v"(bias2[1]), "v"(bias2[2]), "v"(bias2[3]), "v"(bias3));
@@ -546,7 +527,8 @@ __global__ void __launch_bounds__(256) cnn_fused_kernel(const float* __restrict_
     // layer 1: x (1 channel) -> h1 (16), one 16x16x16 step per group: lane group kg holds the
     // three taps of window row min(kg, 2) (converted in pairs) and a zero
     auto a1 = [&](int p) -> bf16x4 {
-      const int r = p / T::H1C, c = p - r * T::H1C;
+      const int pc = min(p, T::H1Px - 1);   // the last group's extra pixels read the last one
+      const int r = pc / T::H1C, c = pc - r * T::H1C;
       const float* xp = sxc + r * T::XC + c + x_row;
       const uint32_t w0 = pack2_bf16(xp[0], xp[1]);
       const uint32_t w1 = pack2_bf16(xp[2], 0.f);
@@ -560,35 +542,52 @@ __global__ void __launch_bounds__(256) cnn_fused_kernel(const float* __restrict_
       f32x4 acca = {0.f, 0.f, 0.f, 0.f}, accb = {0.f, 0.f, 0.f, 0.f};
       acca = mfma16(w1op, aa, acca);
       accb = mfma16(w1op, ab, accb);
-      store4(sh1, T::H1Px, acca, bias1, pa, T::H1C, -2, -2);
-      store4(sh1, T::H1Px, accb, bias1, pb, T::H1C, -2, -2);
+      store4(sh1, T::H1Store, acca, bias1, pa, T::H1C, -2, -2);
+      store4(sh1, T::H1Store, accb, bias1, pb, T::H1C, -2, -2);
     }
     __syncthreads();   // h1 complete; the previous tile's layer 3 is done with the partials
 
-    // layer 2: h1 (16) -> h2 (16).  A wave takes two groups at a time (its groups g and g + 4;
-    // the second repeats the first when there is none): their operands load together and the
-    // two accumulation chains interleave on the matrix core.
-    for (int g = wave; g < T::H2Groups; g += 8) {
-      const int gb = g + 4 < T::H2Groups ? g + 4 : g;
-      const int pa = g * 16 + m, pb = gb * 16 + m;           // < H2Store
-      const int qa = min(pa, T::H2Px - 1), qb = min(pb, T::H2Px - 1);
-      const int ra = qa / T::H2C, ca = qa - ra * T::H2C, rb = qb / T::H2C, cb = qb - rb * T::H2C;
-      const Ops16 oa = load_ops16<T::H1C, T::H1Px>(sh1, ra * T::H1C + ca, kg);
-      const Ops16 ob = load_ops16<T::H1C, T::H1Px>(sh1, rb * T::H1C + cb, kg);
-      f32x4 acca = {0.f, 0.f, 0.f, 0.f}, accb = {0.f, 0.f, 0.f, 0.f};
-      // the wave's priority is raised while it issues its chain, so that the matrix core is
-      // fed while the block's other waves load
-      __builtin_amdgcn_s_setprio(1);
+    // layer 2: h1 (16) -> h2 (16).  The h2 region is two segments of 16 columns; wave w walks
+    // segment w % 2 down half of its rows.  Output row y takes window rows y .. y + 2 of h1,
+    // each as one 16x16x32 step (lane groups kg < 2: column x, kg >= 2: column x + 1, channels
+    // 8 (kg % 2) ..) and one 16x16x16 step (column x + 2, channels 4 kg ..): a window row's
+    // operands serve three output rows, so each row loads only its last window row.
+    {
+      constexpr int RPW = T::H2R / 2;
+      const int x = (wave & 1) * 16 + m, y0 = (wave >> 1) * RPW;
+      auto ldR = [&](int r) -> bf16x8 {
+        return *reinterpret_cast<const bf16x8*>(
+            sh1 + ((kg & 1) * T::H1Store + r * T::H1C + x + (kg >> 1)) * 8);
+      };
+      auto ldD = [&](int r) -> bf16x4 {
+        return *reinterpret_cast<const bf16x4*>(
+            sh1 + ((kg >> 1) * T::H1Store + r * T::H1C + x + 2) * 8 + (kg & 1) * 4);
+      };
+      bf16x8 R0 = ldR(y0), R1 = ldR(y0 + 1);
+      bf16x4 D0 = ldD(y0), D1 = ldD(y0 + 1);
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        acca = mfma32(w2op[s], oa.a[s], acca);
-        accb = mfma32(w2op[s], ob.a[s], accb);
+      for (int i = 0; i < RPW; ++i) {
+        const bf16x8 R2 = ldR(y0 + i + 2);
+        const bf16x4 D2 = ldD(y0 + i + 2);
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        __builtin_amdgcn_s_setprio(1);
+        acc = mfma32(w2r[0], R0, acc);
+        acc = mfma32(w2r[1], R1, acc);
+        acc = mfma32(w2r[2], R2, acc);
+        // a 16x16x16 step that accumulates onto a 16x16x32 step's result needs wait states
+        // the compiler does not insert when the two are back to back (found by the bit-exact
+        // comparison with the layer-by-layer kernel): 16 are given explicitly
+        asm volatile("s_nop 7\n\ts_nop 7" : "+v"(acc));
+        acc = mfma16(w2d[0], D0, acc);
+        acc = mfma16(w2d[1], D1, acc);
+        acc = mfma16(w2d[2], D2, acc);
+        __builtin_amdgcn_s_setprio(0);
+        partials3(acc, (y0 + i) * T::H2C + x);
+        R0 = R1;
+        R1 = R2;
+        D0 = D1;
+        D1 = D2;
       }
-      acca = mfma16(w2op4, oa.a4, acca);
-      accb = mfma16(w2op4, ob.a4, accb);
-      __builtin_amdgcn_s_setprio(0);
-      partials3(acca, pa);
-      partials3(accb, pb);
     }
     if (tn < total_tiles) store_x(sx[buf ^ 1]);
     __syncthreads();   // the partials and the next tile's x region complete
@@ -597,8 +596,9 @@ __global__ void __launch_bounds__(256) cnn_fused_kernel(const float* __restrict_
     // then adds the bias and the residual (two pixels per thread, a row of 32 per half wave)
     float* dst = out + (size_t)b * H * W;
 #pragma unroll
-    for (int k = 0; k < TH * TW / 256; ++k) {
+    for (int k = 0; k < (TH * TW + 255) / 256; ++k) {
       const int e = tid + 256 * k;
+      if (e >= TH * TW) break;
       const int r = e / TW, c = e - r * TW;
       const float* q = sp3 + r * T::H2C + c;
       float sum = q[0];
@@ -612,9 +612,9 @@ __global__ void __launch_bounds__(256) cnn_fused_kernel(const float* __restrict_
 
 }  // namespace
 
-// Output tile of the fused network: 16 x 32 pixels (52 KB of LDS per block, three per CU).  The launch is
+// Output tile of the fused network: 16 x 30 pixels (49 KB of LDS per block, three per CU).  The launch is
 // persistent: as many blocks as the device holds at once, each looping over tiles.
-constexpr int kFuseTH = 16, kFuseTW = 32;
+constexpr int kFuseTH = 16, kFuseTW = 30;
 
 hipError_t launch_cnn_fused(const float* in, const uint16_t* w1, const float* b1,
                             const uint16_t* w2, const float* b2, const uint16_t* w3,

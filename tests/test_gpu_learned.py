@@ -97,7 +97,7 @@ def test_cnn_forward_matches_oracle(gpu_lib):
 def test_cnn_fused_forward_equals_layer_by_layer(gpu_lib):
     """fbp_cnn_forward (one launch, hidden activations in LDS) against the three fbp_cnn_conv
     launches: the same matrix-core operations on the same operands, so equal bit for bit,
-    across tile edges (128 x 96 is 8 x 3 tiles of 16 x 32)."""
+    across tile edges (128 x 96 is 8 x 4 tiles of 16 x 30, the last column of tiles partial)."""
     api = gpu_lib
     import paper_2007_06289_amd.learned as L
     B, H, W = 2, 128, 96

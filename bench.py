@@ -235,7 +235,7 @@ ALGORITHMIC_BYTES_PER_PIXEL = 20   # read the 4 linogram classes (16 N^2 B), wri
 
 
 def pass_model_bytes(kind: str, n: int, levels: list[int]) -> float:
-    """HBM bytes per slice that one launch of each kernel kind moves under this build's pass
+    """HBM bytes per slice that one launch of each kernel kind moves under the library's pass
     design (float32).  This is the design's own traffic model, which includes the round trip
     of the inter-pass intermediate; the method's algorithmic minimum for the whole path is
     ALGORITHMIC_BYTES_PER_PIXEL * N^2 per slice, and the roofline fraction is taken on that.
@@ -351,7 +351,7 @@ def cpu_baseline(lino_cpu, b, a):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the library has no "
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:

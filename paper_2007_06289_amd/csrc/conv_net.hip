@@ -118,7 +118,8 @@ __global__ void cnn_pack_kernel(const float* __restrict__ w, uint16_t* __restric
   packed[e] = f2bf(v);
 }
 
-// CIN in {1, 16} input channels (FP32 image if 1, BF16 NHWC if 16); COUT in {1, 16}.
+// CIN in {1, 16} input channels (FP32 image if 1, BF16 NHWC if 16); COUT in {1, 16}; 16 -> 16
+// runs in cnn_conv16_tile_kernel below.
 // COUT == 16: out16 (BF16 NHWC) = [relu]((acc + bias) [* (mask > 0)]).
 // COUT == 1: out32 (FP32) = acc + bias [+ resid]; from 16 channels, acc is the sum in tap order
 // of the per-tap partials of the pixel's nine neighbours (the K order of the header).
@@ -183,29 +184,10 @@ __global__ void __launch_bounds__(256) cnn_conv_kernel(const float* __restrict__
     }
     return;
   }
+  static_assert(CIN == 1 || COUT == 1, "16 -> 16 runs in cnn_conv16_tile_kernel");
+  if constexpr (CIN == 1) {
   f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-  if constexpr (CIN == 16) {
-    // window rows dy = 0..2 at columns dx = kg / 2 (16x16x32), then column 2 (16x16x16)
-#pragma unroll
-    for (int s = 0; s < 3; ++s) {
-      const int yy = y + s - 1, xx = x + (kg >> 1) - 1;
-      bf16x8 a = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
-      if (inside(yy, xx))
-        a = *reinterpret_cast<const bf16x8*>(in16 + (((size_t)b * H + yy) * W + xx) * 16 +
-                                             (kg & 1) * 8);
-      acc = mfma32(wop[s * 64 + lane], a, acc);
-    }
-    asm volatile("s_nop 7\n\ts_nop 7" : "+v"(acc));   // as in the fused kernel's layer 2
-#pragma unroll
-    for (int s = 0; s < 3; ++s) {
-      const int yy = y + s - 1, xx = x + 1;
-      bf16x4 a = bf16x4{0, 0, 0, 0};
-      if (inside(yy, xx))
-        a = *reinterpret_cast<const bf16x4*>(in16 + (((size_t)b * H + yy) * W + xx) * 16 +
-                                             4 * kg);
-      acc = mfma16(reinterpret_cast<const bf16x4*>(wop)[3 * 128 + s * 64 + lane], a, acc);
-    }
-  } else {
+  {
     bf16x4 a;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -230,6 +212,93 @@ __global__ void __launch_bounds__(256) cnn_conv_kernel(const float* __restrict__
     *reinterpret_cast<uint2*>(out16 + pix * 16 + 4 * kg) = w;
   } else {
     if (kg == 0) out32[pix] = acc[0] + (bias ? bias[0] : 0.f) + (resid ? resid[pix] : 0.f);
+  }
+  }
+}
+
+// 16 -> 16 convolution over tiles of 16 output rows x 32 columns: the input pixels the tile
+// needs (18 x 34, zero outside the image) are staged once in LDS, in two planes of 8 channels,
+// and each wave walks one 16-column segment down 8 output rows as the fused kernel's layer 2
+// does, with the same operands and matrix-core steps (the K order of the header), so the two
+// give the same h2 bit for bit; each input pixel is read from memory once per tile.  The
+// epilogue: bias, then the mask (the ReLU derivative of the layer below, in the backward
+// pass), BF16, then the optional ReLU.
+constexpr int kC16TH = 16, kC16TW = 32;
+__global__ void __launch_bounds__(256) cnn_conv16_tile_kernel(const uint16_t* __restrict__ in16,
+                                                              const bf16x8* __restrict__ wop,
+                                                              const float* __restrict__ bias,
+                                                              const uint16_t* __restrict__ mask,
+                                                              uint16_t* __restrict__ out16,
+                                                              int relu, int H, int W, int tiles_x,
+                                                              int tiles_per_img) {
+  constexpr int RR = kC16TH + 2, RC = kC16TW + 2, RP = RR * RC;
+  __shared__ __align__(16) uint16_t sin16[2 * RP * 8];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int m = lane & 15, kg = lane >> 4;
+  const int b = blockIdx.x / tiles_per_img, t = blockIdx.x - b * tiles_per_img;
+  const int Y0 = (t / tiles_x) * kC16TH, X0 = (t % tiles_x) * kC16TW;
+  // 16 bytes (8 channels of plane h) of one region pixel per step
+  for (int e = tid; e < 2 * RP; e += 256) {
+    const int q = e >> 1, h = e & 1;
+    const int r = q / RC, c = q - r * RC;
+    const int gy = Y0 - 1 + r, gx = X0 - 1 + c;
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (gy >= 0 && gy < H && gx >= 0 && gx < W)
+      v = *reinterpret_cast<const uint4*>(in16 + (((size_t)b * H + gy) * W + gx) * 16 + 8 * h);
+    *reinterpret_cast<uint4*>(sin16 + (h * RP + q) * 8) = v;
+  }
+  bf16x8 wr[3];
+  bf16x4 wd[3];
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    wr[s] = wop[s * 64 + lane];
+    wd[s] = reinterpret_cast<const bf16x4*>(wop)[3 * 128 + s * 64 + lane];
+  }
+  float bs[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) bs[i] = bias ? bias[4 * kg + i] : 0.f;
+  __syncthreads();
+  const int x = (wave & 1) * 16 + m, r0 = (wave >> 1) * (kC16TH / 2);
+  auto ldR = [&](int r) -> bf16x8 {
+    return *reinterpret_cast<const bf16x8*>(sin16 + ((kg & 1) * RP + r * RC + x + (kg >> 1)) * 8);
+  };
+  auto ldD = [&](int r) -> bf16x4 {
+    return *reinterpret_cast<const bf16x4*>(sin16 + ((kg >> 1) * RP + r * RC + x + 2) * 8 +
+                                            (kg & 1) * 4);
+  };
+  bf16x8 R0 = ldR(r0), R1 = ldR(r0 + 1);
+  bf16x4 D0 = ldD(r0), D1 = ldD(r0 + 1);
+  const int gx = X0 + x;
+#pragma unroll
+  for (int i = 0; i < kC16TH / 2; ++i) {
+    const bf16x8 R2 = ldR(r0 + i + 2);
+    const bf16x4 D2 = ldD(r0 + i + 2);
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = mfma32(wr[0], R0, acc);
+    acc = mfma32(wr[1], R1, acc);
+    acc = mfma32(wr[2], R2, acc);
+    asm volatile("s_nop 7\n\ts_nop 7" : "+v"(acc));   // as in the fused kernel's layer 2
+    acc = mfma16(wd[0], D0, acc);
+    acc = mfma16(wd[1], D1, acc);
+    acc = mfma16(wd[2], D2, acc);
+    const int gy = Y0 + r0 + i;
+    if (gy < H && gx < W) {
+      const size_t pix = ((size_t)b * H + gy) * W + gx;
+      float v[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        v[j] = acc[j] + bs[j];
+        if (mask && !(bf2f(mask[pix * 16 + 4 * kg + j]) > 0.f)) v[j] = 0.f;
+      }
+      uint2 w = pack4_bf16(v[0], v[1], v[2], v[3]);
+      if (relu) w = make_uint2(relu_bf16x2(w.x), relu_bf16x2(w.y));
+      *reinterpret_cast<uint2*>(out16 + pix * 16 + 4 * kg) = w;
+    }
+    R0 = R1;
+    R1 = R2;
+    D0 = D1;
+    D1 = D2;
   }
 }
 
@@ -657,9 +726,13 @@ hipError_t launch_cnn_conv(int cin, int cout, const float* in32, const uint16_t*
   if (cin == 1 && cout == 16)
     hipLaunchKernelGGL((cnn_conv_kernel<1, 16>), grid, dim3(256), 0, stream, in32, in16, w8, bias,
                        mask, resid, out16, out32, relu, H, W, groups);
-  else if (cin == 16 && cout == 16)
-    hipLaunchKernelGGL((cnn_conv_kernel<16, 16>), grid, dim3(256), 0, stream, in32, in16, w8,
-                       bias, mask, resid, out16, out32, relu, H, W, groups);
+  else if (cin == 16 && cout == 16) {
+    const int tiles_x = (W + kC16TW - 1) / kC16TW, tiles_y = (H + kC16TH - 1) / kC16TH;
+    const long long tiles = (long long)batch * tiles_x * tiles_y;
+    if (tiles > 0x7fffffffll) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(cnn_conv16_tile_kernel, dim3((unsigned)tiles), dim3(256), 0, stream, in16,
+                       w8, bias, mask, out16, relu, H, W, tiles_x, tiles_x * tiles_y);
+  }
   else if (cin == 16 && cout == 1)
     hipLaunchKernelGGL((cnn_conv_kernel<16, 1>), grid, dim3(256), 0, stream, in32, in16, w8, bias,
                        mask, resid, out16, out32, relu, H, W, groups);

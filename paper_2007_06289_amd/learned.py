@@ -231,7 +231,7 @@ def train(model: LearnedFBP, lino: torch.Tensor, target: torch.Tensor, mask: tor
         opt.zero_grad()
         loss.backward()
         opt.step()
-        hist.append(float(loss))
+        hist.append(float(loss.detach()))
         if log and (it % 20 == 0 or it == steps - 1):
             log(f"step {it}: relative MSE {hist[-1]:.5f}")
     return hist

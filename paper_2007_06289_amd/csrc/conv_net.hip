@@ -118,101 +118,127 @@ __global__ void cnn_pack_kernel(const float* __restrict__ w, uint16_t* __restric
   packed[e] = f2bf(v);
 }
 
-// CIN in {1, 16} input channels (FP32 image if 1, BF16 NHWC if 16); COUT in {1, 16}; 16 -> 16
-// runs in cnn_conv16_tile_kernel below.
-// COUT == 16: out16 (BF16 NHWC) = [relu]((acc + bias) [* (mask > 0)]).
-// COUT == 1: out32 (FP32) = acc + bias [+ resid]; from 16 channels, acc is the sum in tap order
-// of the per-tap partials of the pixel's nine neighbours (the K order of the header).
-template <int CIN, int COUT>
-__global__ void __launch_bounds__(256) cnn_conv_kernel(const float* __restrict__ in32,
-                                                       const uint16_t* __restrict__ in16,
-                                                       const bf16x8* __restrict__ wop,
-                                                       const float* __restrict__ bias,
-                                                       const uint16_t* __restrict__ mask,
-                                                       const float* __restrict__ resid,
-                                                       uint16_t* __restrict__ out16,
-                                                       float* __restrict__ out32, int relu, int H,
-                                                       int W, long long groups) {
-  const int lane = threadIdx.x & 63;
-  const long long gi = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);   // 16-pixel group
-  if (gi >= groups) return;
-  const int gpr = W >> 4;
-  const int xg = (int)(gi % gpr);
-  const long long by = gi / gpr;
-  const int y = (int)(by % H);
-  const int b = (int)(by / H);
+// The epilogue of a 16-channel output, shared by the per-layer kernels: lane (m, kg) holds
+// channels 4 kg .. + 3 of pixel pix; bias, then the mask (kept where > 0: the ReLU derivative
+// of the layer below, in the backward pass), BF16, then the optional ReLU, one 8-byte store.
+__device__ __forceinline__ void store_c16(const f32x4& acc, const float (&bs)[4],
+                                          const uint16_t* __restrict__ mask, int relu,
+                                          uint16_t* __restrict__ out16, size_t pix, int kg) {
+  float v[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) v[j] = acc[j] + bs[j];
+  if (mask) {
+    const uint2 mw = *reinterpret_cast<const uint2*>(mask + pix * 16 + 4 * kg);
+    const uint16_t mh[4] = {(uint16_t)mw.x, (uint16_t)(mw.x >> 16), (uint16_t)mw.y,
+                            (uint16_t)(mw.y >> 16)};
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (!(bf2f(mh[j]) > 0.f)) v[j] = 0.f;
+  }
+  uint2 w = pack4_bf16(v[0], v[1], v[2], v[3]);
+  if (relu) w = make_uint2(relu_bf16x2(w.x), relu_bf16x2(w.y));
+  *reinterpret_cast<uint2*>(out16 + pix * 16 + 4 * kg) = w;
+}
+
+// 1 -> 16 convolution (FP32 image in, BF16 NHWC out) over tiles of 32 x 32 output pixels: the
+// 34 x 34 input pixels a tile needs (zero outside the image) are staged once in LDS, and each
+// wave walks one 16-column segment down 16 rows, one 16x16x16 step per output row with the
+// operands of the K order in the header (lane group g < 3: window row g, columns 0..2 and a
+// zero; group 3 zeros).
+constexpr int kC1TH = 32, kC1TW = 32;
+__global__ void __launch_bounds__(256) cnn_conv1_tile_kernel(const float* __restrict__ in32,
+                                                             const bf16x8* __restrict__ wop,
+                                                             const float* __restrict__ bias,
+                                                             const uint16_t* __restrict__ mask,
+                                                             uint16_t* __restrict__ out16,
+                                                             int relu, int H, int W, int tiles_x,
+                                                             int tiles_per_img) {
+  constexpr int RR = kC1TH + 2, RC = kC1TW + 2;
+  __shared__ float sx[RR * RC];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int m = lane & 15, kg = lane >> 4;
-  const int x = (xg << 4) + m;
-  auto inside = [&](int yy, int xx) { return yy >= 0 && yy < H && xx >= 0 && xx < W; };
-  if constexpr (CIN == 16 && COUT == 1) {
-    // The group's outputs (y, x), x = 16 xg + m, read the partials of rows y - 1 .. y + 1 at
-    // neighbourhood columns 0 .. 17 (image columns 16 xg - 1 .. 16 xg + 16): per row one
-    // 16x16x16 step for columns 0 .. 15 and one for 16, 17 (lanes m < 2).  The wave keeps them
-    // in its own LDS area [tap][row][column].
-    __shared__ float spart[4][9 * 3 * 32];
-    float* sp = spart[threadIdx.x >> 6];
-    const bf16x4 at = reinterpret_cast<const bf16x4*>(wop)[lane];
-#pragma unroll
-    for (int rr = 0; rr < 3; ++rr) {
-      const int yy = y + rr - 1;
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int col = 16 * h + m;
-        const int xx = (xg << 4) - 1 + col;
-        const bool use = h == 0 || m < 2;
-        bf16x4 bv = bf16x4{0, 0, 0, 0};
-        if (use && inside(yy, xx))
-          bv = *reinterpret_cast<const bf16x4*>(in16 + (((size_t)b * H + yy) * W + xx) * 16 +
-                                                4 * kg);
-        const f32x4 pt = mfma16(at, bv, f32x4{0.f, 0.f, 0.f, 0.f});
-        if (use) {
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            if (4 * kg + i < 9) sp[((4 * kg + i) * 3 + rr) * 32 + col] = pt[i];
-        }
-      }
-    }
-    // the wave's partials are in LDS before any lane reads them
-    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-    if (kg == 0) {
-      const float* q = sp + m;
-      float sum = q[0];
-#pragma unroll
-      for (int t = 1; t < 9; ++t) sum += q[(t * 3 + t / 3) * 32 + t % 3];
-      const size_t pix = ((size_t)b * H + y) * W + x;
-      out32[pix] = sum + (bias ? bias[0] : 0.f) + (resid ? resid[pix] : 0.f);
-    }
-    return;
+  const int b = blockIdx.x / tiles_per_img, t = blockIdx.x - b * tiles_per_img;
+  const int Y0 = (t / tiles_x) * kC1TH, X0 = (t % tiles_x) * kC1TW;
+  for (int e = tid; e < RR * RC; e += 256) {
+    const int r = e / RC, c = e - r * RC;
+    const int gy = Y0 - 1 + r, gx = X0 - 1 + c;
+    sx[e] = (gy >= 0 && gy < H && gx >= 0 && gx < W) ? in32[((size_t)b * H + gy) * W + gx] : 0.f;
   }
-  static_assert(CIN == 1 || COUT == 1, "16 -> 16 runs in cnn_conv16_tile_kernel");
-  if constexpr (CIN == 1) {
-  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-  {
-    bf16x4 a;
+  const bf16x4 wa = reinterpret_cast<const bf16x4*>(wop)[lane];
+  float bs[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int yy = y + kg - 1, xx = x + j - 1;
-      float v = 0.f;
-      if (kg < 3 && j < 3 && inside(yy, xx)) v = in32[((size_t)b * H + yy) * W + xx];
-      a[j] = (short)f2bf(v);
-    }
-    acc = mfma16(reinterpret_cast<const bf16x4*>(wop)[lane], a, acc);
+  for (int i = 0; i < 4; ++i) bs[i] = bias ? bias[4 * kg + i] : 0.f;
+  __syncthreads();
+  const int x = (wave & 1) * 16 + m, r0 = (wave >> 1) * (kC1TH / 2);
+  const int gx = X0 + x;
+  if (gx >= W) return;   // W is a multiple of 16: whole segments are in or out
+  const float* q = sx + (r0 + (kg < 3 ? kg : 0)) * RC + x;
+#pragma unroll 4
+  for (int i = 0; i < kC1TH / 2; ++i) {
+    const int gy = Y0 + r0 + i;
+    if (gy >= H) break;
+    bf16x4 a = __builtin_bit_cast(bf16x4, make_uint2(pack2_bf16(q[i * RC], q[i * RC + 1]),
+                                                       pack2_bf16(q[i * RC + 2], 0.f)));
+    if (kg == 3) a = bf16x4{0, 0, 0, 0};
+    const f32x4 acc = mfma16(wa, a, f32x4{0.f, 0.f, 0.f, 0.f});
+    store_c16(acc, bs, mask, relu, out16, ((size_t)b * H + gy) * W + gx, kg);
   }
-  // lane (m, kg): pixel x, channels 4 kg .. 4 kg + 3
-  const size_t pix = ((size_t)b * H + y) * W + x;
-  if constexpr (COUT == 16) {
-    float v[4];
+}
+
+// 16 -> 1 convolution (BF16 NHWC in, FP32 out) over tiles of 32 rows x 30 columns: the nine
+// per-tap partial sums (K order of the header) of each input pixel of the tile's 34 x 32
+// neighbourhood, two 16-pixel groups per row, go to LDS as nine FP32 planes; an output pixel
+// is the sum of its nine neighbours' partials in tap order, then the bias and the residual.
+constexpr int kC3TH = 32, kC3TW = 30;
+__global__ void __launch_bounds__(256) cnn_conv16to1_tile_kernel(const uint16_t* __restrict__ in16,
+                                                                 const bf16x8* __restrict__ wop,
+                                                                 const float* __restrict__ bias,
+                                                                 const float* __restrict__ resid,
+                                                                 float* __restrict__ out32, int H,
+                                                                 int W, int tiles_x,
+                                                                 int tiles_per_img) {
+  constexpr int PR = kC3TH + 2, PC = kC3TW + 2;
+  static_assert(PC == 32 && (2 * PR) % 4 == 0, "two groups per row, whole rounds of 4 waves");
+  constexpr int PS = PR * PC + 4;   // plane stride: lane groups 0..2 land in different banks
+  __shared__ float sp[9 * PS];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int m = lane & 15, kg = lane >> 4;
+  const int b = blockIdx.x / tiles_per_img, t = blockIdx.x - b * tiles_per_img;
+  const int Y0 = (t / tiles_x) * kC3TH, X0 = (t % tiles_x) * kC3TW;
+  const bf16x4 at = reinterpret_cast<const bf16x4*>(wop)[lane];
+  constexpr int PER_WAVE = 2 * PR / 4;
+  bf16x4 bv[PER_WAVE];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      v[i] = acc[i] + (bias ? bias[4 * kg + i] : 0.f);
-      if (mask && !(bf2f(mask[pix * 16 + 4 * kg + i]) > 0.f)) v[i] = 0.f;
-    }
-    uint2 w = pack4_bf16(v[0], v[1], v[2], v[3]);
-    if (relu) w = make_uint2(relu_bf16x2(w.x), relu_bf16x2(w.y));
-    *reinterpret_cast<uint2*>(out16 + pix * 16 + 4 * kg) = w;
-  } else {
-    if (kg == 0) out32[pix] = acc[0] + (bias ? bias[0] : 0.f) + (resid ? resid[pix] : 0.f);
+  for (int k = 0; k < PER_WAVE; ++k) {   // group wave + 4 k: row q / 2, columns 16 (q % 2) + m
+    const int q = wave + 4 * k, r = q >> 1, col = ((q & 1) << 4) + m;
+    const int gy = Y0 - 1 + r, gx = X0 - 1 + col;
+    bv[k] = bf16x4{0, 0, 0, 0};
+    if (gy >= 0 && gy < H && gx >= 0 && gx < W)
+      bv[k] = *reinterpret_cast<const bf16x4*>(in16 + (((size_t)b * H + gy) * W + gx) * 16 +
+                                               4 * kg);
   }
+#pragma unroll
+  for (int k = 0; k < PER_WAVE; ++k) {
+    const int q = wave + 4 * k, r = q >> 1, col = ((q & 1) << 4) + m;
+    const f32x4 pt = mfma16(at, bv[k], f32x4{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (4 * kg + i < 9) sp[(4 * kg + i) * PS + r * PC + col] = pt[i];
+  }
+  __syncthreads();
+  const float b0 = bias ? bias[0] : 0.f;
+  for (int e = tid; e < kC3TH * kC3TW; e += 256) {
+    const int r = e / kC3TW, c = e - r * kC3TW;
+    const int gy = Y0 + r, gx = X0 + c;
+    if (gy >= H || gx >= W) continue;
+    const float* q = sp + r * PC + c;
+    float sum = q[0];
+#pragma unroll
+    for (int tp = 1; tp < 9; ++tp) sum += q[tp * PS + (tp / 3) * PC + tp % 3];
+    const size_t pix = ((size_t)b * H + gy) * W + gx;
+    out32[pix] = sum + b0 + (resid ? resid[pix] : 0.f);
   }
 }
 
@@ -283,18 +309,7 @@ __global__ void __launch_bounds__(256) cnn_conv16_tile_kernel(const uint16_t* __
     acc = mfma16(wd[1], D1, acc);
     acc = mfma16(wd[2], D2, acc);
     const int gy = Y0 + r0 + i;
-    if (gy < H && gx < W) {
-      const size_t pix = ((size_t)b * H + gy) * W + gx;
-      float v[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        v[j] = acc[j] + bs[j];
-        if (mask && !(bf2f(mask[pix * 16 + 4 * kg + j]) > 0.f)) v[j] = 0.f;
-      }
-      uint2 w = pack4_bf16(v[0], v[1], v[2], v[3]);
-      if (relu) w = make_uint2(relu_bf16x2(w.x), relu_bf16x2(w.y));
-      *reinterpret_cast<uint2*>(out16 + pix * 16 + 4 * kg) = w;
-    }
+    if (gy < H && gx < W) store_c16(acc, bs, mask, relu, out16, ((size_t)b * H + gy) * W + gx, kg);
     R0 = R1;
     R1 = R2;
     D0 = D1;
@@ -720,27 +735,25 @@ hipError_t launch_cnn_conv(int cin, int cout, const float* in32, const uint16_t*
                            const uint16_t* wop, const float* bias, const uint16_t* mask,
                            const float* resid, uint16_t* out16, float* out32, int relu, int batch,
                            int H, int W, hipStream_t stream) {
-  const long long groups = (long long)batch * H * (W / 16);
-  const dim3 grid((unsigned)((groups + 3) / 4));
   const bf16x8* w8 = reinterpret_cast<const bf16x8*>(wop);
-  if (cin == 1 && cout == 16)
-    hipLaunchKernelGGL((cnn_conv_kernel<1, 16>), grid, dim3(256), 0, stream, in32, in16, w8, bias,
-                       mask, resid, out16, out32, relu, H, W, groups);
-  else if (cin == 16 && cout == 16) {
-    const int tiles_x = (W + kC16TW - 1) / kC16TW, tiles_y = (H + kC16TH - 1) / kC16TH;
-    const long long tiles = (long long)batch * tiles_x * tiles_y;
-    if (tiles > 0x7fffffffll) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(cnn_conv16_tile_kernel, dim3((unsigned)tiles), dim3(256), 0, stream, in16,
-                       w8, bias, mask, out16, relu, H, W, tiles_x, tiles_x * tiles_y);
-  }
-  else if (cin == 16 && cout == 1)
-    hipLaunchKernelGGL((cnn_conv_kernel<16, 1>), grid, dim3(256), 0, stream, in32, in16, w8, bias,
-                       mask, resid, out16, out32, relu, H, W, groups);
-  else if (cin == 1 && cout == 1)
-    hipLaunchKernelGGL((cnn_conv_kernel<1, 1>), grid, dim3(256), 0, stream, in32, in16, w8, bias,
-                       mask, resid, out16, out32, relu, H, W, groups);
+  int th, tw;
+  if (cin == 1 && cout == 16) th = kC1TH, tw = kC1TW;
+  else if (cin == 16 && cout == 16) th = kC16TH, tw = kC16TW;
+  else if (cin == 16 && cout == 1) th = kC3TH, tw = kC3TW;
+  else return hipErrorInvalidValue;
+  const int tiles_x = (W + tw - 1) / tw, tiles_y = (H + th - 1) / th;
+  const long long tiles = (long long)batch * tiles_x * tiles_y;
+  if (tiles > 0x7fffffffll) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)tiles);
+  if (cin == 1)
+    hipLaunchKernelGGL(cnn_conv1_tile_kernel, grid, dim3(256), 0, stream, in32, w8, bias, mask,
+                       out16, relu, H, W, tiles_x, tiles_x * tiles_y);
+  else if (cout == 16)
+    hipLaunchKernelGGL(cnn_conv16_tile_kernel, grid, dim3(256), 0, stream, in16, w8, bias, mask,
+                       out16, relu, H, W, tiles_x, tiles_x * tiles_y);
   else
-    return hipErrorInvalidValue;
+    hipLaunchKernelGGL(cnn_conv16to1_tile_kernel, grid, dim3(256), 0, stream, in16, w8, bias,
+                       resid, out32, H, W, tiles_x, tiles_x * tiles_y);
   return hipGetLastError();
 }
 

@@ -207,11 +207,6 @@ class LearnedFBP:
         self.plan.close()
 
 
-def masked_mse(x: torch.Tensor, y: torch.Tensor, mask: torch.Tensor) -> torch.Tensor:
-    d = (x - y)[:, mask]
-    return (d * d).mean()
-
-
 def train(model: LearnedFBP, lino: torch.Tensor, target: torch.Tensor, mask: torch.Tensor,
           steps: int = 200, batch: int = 8, lr_coef: float = 1e-3, lr_cnn: float = 1e-3,
           seed: int = 0, log=None):
@@ -223,18 +218,27 @@ def train(model: LearnedFBP, lino: torch.Tensor, target: torch.Tensor, mask: tor
         groups.append({"params": list(model.cnn.values()), "lr": lr_cnn})
     opt = torch.optim.Adam(groups)
     scale = float((target[:, mask] ** 2).mean())
+    # Everything a step needs from the host is ready before the loop, so that the host waits on
+    # the device only where the coefficients pass through it (their gradient and the plan's
+    # recursion tables): the mini-batches (the same draws as one randperm per step), the mask
+    # as a factor and the count of masked pixels, and the losses, read back at the end.
+    picks = torch.stack([torch.randperm(lino.shape[0], generator=g)[:batch]
+                         for _ in range(steps)]).to(lino.device)
+    maskf = mask.to(device=lino.device, dtype=torch.float32)
+    per_slice = int(mask.sum())
     hist = []
     for it in range(steps):
-        idx = torch.randperm(lino.shape[0], generator=g)[:batch].to(lino.device)
+        idx = picks[it]
         out = model(lino[idx])
-        loss = masked_mse(out, target[idx], mask) / scale
+        d = (out - target[idx]) * maskf
+        loss = (d * d).sum() / (idx.numel() * per_slice * scale)
         opt.zero_grad()
         loss.backward()
         opt.step()
-        hist.append(float(loss.detach()))
+        hist.append(loss.detach())
         if log and (it % 20 == 0 or it == steps - 1):
-            log(f"step {it}: relative MSE {hist[-1]:.5f}")
-    return hist
+            log(f"step {it}: relative MSE {float(hist[-1]):.5f}")
+    return torch.stack(hist).tolist() if hist else []
 
 
 @torch.no_grad()

@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--rocprof-summary", metavar="DIR",
                     help="summarise rocprofv3 csv output under DIR (subfolders trace, fetch, "
                          "write, copyf, copyw, sq, sq2) as text for the profiles folder, and exit")
+    ap.add_argument("--rocprof-kernel-table", metavar="DIR",
+                    help="print the per-kernel table (calls, average and total time, share) of "
+                         "the rocprofv3 --stats csv files under DIR, and exit")
     ap.add_argument("--profile", default=None,
                     help="profile summary whose HBM counters fill roofline.traffic when its "
                          "kernel-source hash matches (default: the one for this workload)")
@@ -89,6 +92,44 @@ def _kind(name: str):
         if key in name:
             return kind
     return None
+
+
+def _short_kernel_name(name: str) -> str:
+    """A demangled kernel name without its return type, namespaces and argument list."""
+    name = name.replace("(anonymous namespace)::", "").replace("fhtfbp::", "")
+    name = name.replace("at::native::", "")
+    if name.startswith("void "):
+        name = name[5:]
+    depth, out = 0, []
+    for ch in name:
+        depth += ch == "<"
+        depth -= ch == ">"
+        if ch == "(" and depth == 0:
+            break
+        out.append(ch)
+    return "".join(out)
+
+
+def rocprof_kernel_table(d: str, top: int = 24) -> str:
+    """Per-kernel table of a rocprofv3 --stats run (its *kernel_stats.csv files under d): calls,
+    average and total duration, share of all kernel time, the largest totals first."""
+    import csv
+    import glob
+
+    rows = []
+    for f in sorted(glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)):
+        with open(f) as fh:
+            rows += list(csv.DictReader(fh))
+    total = sum(float(r["TotalDurationNs"]) for r in rows) or 1.0
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = [f"{'kernel':58s} {'calls':>6s} {'avg_us':>10s} {'total_ms':>10s} {'share':>6s}"]
+    for r in rows[:top]:
+        t = float(r["TotalDurationNs"])
+        lines.append(f"{_short_kernel_name(r['Name'])[:58]:58s} {int(r['Calls']):6d} "
+                     f"{float(r['AverageNs']) / 1e3:10.1f} {t / 1e6:10.2f} "
+                     f"{100 * t / total:5.1f}%")
+    lines.append(f"all kernels: {total / 1e6:.1f} ms")
+    return "\n".join(lines)
 
 
 def rocprof_summary(d: str, n: int, batch: int, order: int) -> str:
@@ -359,6 +400,9 @@ def main():
         return
     if args.rocprof_summary:
         print(rocprof_summary(args.rocprof_summary, args.n, args.batch, args.order))
+        return
+    if args.rocprof_kernel_table:
+        print(rocprof_kernel_table(args.rocprof_kernel_table))
         return
     import torch
     import fbp_inputs as I

@@ -465,8 +465,8 @@ __global__ void __launch_bounds__(256) cnn_reduce_kernel(const float* __restrict
 // side, zero outside the image) into LDS, computes h1 over the tile plus two pixels of halo
 // (BF16 in LDS, zero outside the image: the zero padding of the next layer) and h2 over the
 // tile plus one, whose per-tap partials for layer 3 go to LDS instead of h2 itself, and writes
-// the tile.  Each layer issues the same matrix-core operations with the same operands as
-// cnn_conv_kernel (same K order, same BF16 roundings, bias then ReLU, the partials summed in
+// the tile.  Each layer issues the same matrix-core operations with the same operands as the
+// per-layer kernels (same K order, same BF16 roundings, bias then ReLU, the partials summed in
 // the same order, then the residual), so the image equals the three separate launches bit for
 // bit; only h1 and h2 never go to HBM.  A group is 16 pixels (layer 1: consecutive in the
 // region's row-major order; layer 2: 16 columns of one row); lane (m, kg) of a wave ends with

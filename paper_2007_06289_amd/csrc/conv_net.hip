@@ -322,10 +322,13 @@ __global__ void __launch_bounds__(256) cnn_conv16_tile_kernel(const uint16_t* __
 //   dw[co][ci][tap] = sum_p dz[p][co] in[p + off(tap)][ci],   db[co] = sum_p dz[p][co].
 // dz has COUT channels (FP32 image if 1, BF16 NHWC if 16); in has CIN channels (same rule).
 // Each block covers `rows` image rows x 64 columns of one slice and writes its sums to
-// partial[block][COUT * CIN * 9 + COUT].  Thread co * CIN + ci holds the nine taps of the
-// channel pair (co, ci), and the bias of co when ci = 0: along a row, the three input values
-// of each window row slide through registers, so one dz value and three new input values feed
-// nine FMAs.  Every sum runs over the row's pixels in order, rows in order.  The input rows
+// partial[block][COUT * CIN * 9 + COUT].  With 16 x 16 channel pairs, thread co * CIN + ci
+// holds the nine taps of the pair (co, ci), and the bias of co when ci = 0: along a row, the
+// three input values of each window row slide through registers, so one dz value and three new
+// input values feed nine FMAs, and every sum runs over the row's pixels in order, rows in
+// order.  With 16 pairs, thread pair + 16 s takes the columns s, s + 16, s + 32, s + 48 of
+// each row (in that order, rows in order) and the 16 column sets' sums are added in set order
+// at the end, so all 256 threads work.  The input rows
 // y - 1, y, y + 1 sit in a ring of three LDS rows (row yy in slot (yy + 3) % 3), so each row
 // is staged once; a thread stages 8 channels of a pixel from one 16-byte load.
 template <int CIN, int COUT>
@@ -338,7 +341,9 @@ __global__ void __launch_bounds__(256) cnn_wgrad_kernel(const float* __restrict_
   constexpr int NW = COUT * CIN * 9;
   constexpr int NOUT = NW + COUT;
   constexpr int XS = 64;
-  static_assert(COUT * CIN <= 256, "one thread per channel pair");
+  constexpr int P = COUT * CIN;       // channel pairs
+  constexpr int S = 256 / P;          // column sets per pair
+  static_assert(P <= 256 && 256 % P == 0 && XS % S == 0, "whole column sets per pair");
   __shared__ __align__(16) float sdz[XS][COUT];
   __shared__ __align__(16) float sin_[3][XS + 2][CIN];
   const int cols = W / XS;
@@ -347,8 +352,8 @@ __global__ void __launch_bounds__(256) cnn_wgrad_kernel(const float* __restrict_
   const int cb = rest % cols, b = rest / cols;
   const int x0 = cb * XS;
   const int tid = threadIdx.x;
-  const int co = tid / CIN, ci = tid % CIN;
-  const bool active = tid < COUT * CIN;
+  const int pair = tid % P, set = tid / P;
+  const int co = pair / CIN, ci = pair % CIN;
 
   // 8 BF16 values of one 16-byte load as FP32, stored as two float4
   auto store8 = [](float* d, const uint4& v) {
@@ -407,7 +412,22 @@ __global__ void __launch_bounds__(256) cnn_wgrad_kernel(const float* __restrict_
     stage_in(y + 1);
     stage_dz(y);
     __syncthreads();
-    if (active) {
+    if constexpr (S > 1) {
+      // column set `set`: columns set, set + S, ...; with 16 pairs a wave's reads of one window
+      // value are 64 consecutive floats
+#pragma unroll
+      for (int k = 0; k < XS / S; ++k) {
+        const int xx = set + S * k;
+        const float d = sdz[xx][co];
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+          const float* r = &sin_[(y + dy + 2) % 3][xx][ci];
+#pragma unroll
+          for (int dx = 0; dx < 3; ++dx) acc[3 * dy + dx] = fmaf(d, r[dx * CIN], acc[3 * dy + dx]);
+        }
+        accb += d;
+      }
+    } else {
       const float* r[3];
 #pragma unroll
       for (int dy = 0; dy < 3; ++dy) r[dy] = &sin_[(y + dy + 2) % 3][0][ci];
@@ -434,7 +454,24 @@ __global__ void __launch_bounds__(256) cnn_wgrad_kernel(const float* __restrict_
       }
     }
   }
-  if (active) {
+  if constexpr (S > 1) {
+    // the column sets' sums, added in set order
+    __shared__ float sred[256][10];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) sred[tid][k] = acc[k];
+    sred[tid][9] = accb;
+    __syncthreads();
+    if (tid < P) {
+#pragma unroll
+      for (int k = 0; k < 10; ++k) {
+        float v = sred[tid][k];
+        for (int st = 1; st < S; ++st) v += sred[tid + P * st][k];
+        if (k < 9) acc[k] = v;
+        else accb = v;
+      }
+    }
+  }
+  if (tid < P) {
     float* dst = partial + (size_t)blockIdx.x * NOUT;
 #pragma unroll
     for (int k = 0; k < 9; ++k) dst[(co * CIN + ci) * 9 + k] = acc[k];

@@ -480,6 +480,125 @@ __global__ void __launch_bounds__(256) cnn_wgrad_kernel(const float* __restrict_
 }
 
 // out[o] = sum over blocks of partial[block][o], fixed order, accumulated in double.
+// Weight and bias gradients of the 16 -> 16 convolution on the matrix cores, for the blocks
+// and partial layout of cnn_wgrad_kernel: dw[co][ci][tap] = sum_p dz[p][co] in[p + off(tap)][ci]
+// as 16x16x32 BF16 products with A[co][k] = dz at 32 consecutive pixels of a row and B[k][ci] =
+// the input at the same pixels moved by the tap (products of BF16 values are exact, sums are
+// FP32), and db[co] = sum_p dz[p][co] as one more product against B = 1.  A block covers 16 rows
+// x 64 columns of one slice in two stages of 8 rows: the stage's dz rows and input rows (one
+// above and one below, columns -2 .. 65, zero outside the image) go to LDS channel-major, one
+// row of pixels per channel, so that a lane's 8 pixels of one channel are one 16-byte read;
+// the input one column left or right (dx = 0, 2) comes from that read and a neighbouring word
+// by funnel shifts.  Wave w takes rows w and w + 4 of each stage; the four waves' sums are
+// added in wave order at the end.
+constexpr int kWgStage = 8;
+constexpr int kWgXP = 88;   // input plane row: element 8 + xx for column xx (16-byte aligned reads)
+constexpr int kWgDP = 72;   // dz plane row: element xx
+__global__ void __launch_bounds__(256) cnn_wgrad16_kernel(const uint16_t* __restrict__ dz16,
+                                                          const uint16_t* __restrict__ in16,
+                                                          float* __restrict__ partial, int H,
+                                                          int W, int rows) {
+  constexpr int XS = 64, XR = kWgStage + 2, NW = 16 * 16 * 9, NOUT = NW + 16;
+  constexpr int XWORDS = XR * 16 * kWgXP / 2, DWORDS = kWgStage * 16 * kWgDP / 2;
+  static_assert(XWORDS + DWORDS >= 4 * 10 * 64 * 4, "the wave sums fit in the staging area");
+  __shared__ __align__(16) uint32_t sxd[XWORDS + DWORDS];
+  uint32_t* sx = sxd;
+  uint32_t* sd = sxd + XWORDS;
+  const int cols = W / XS;
+  const int nrb = (H + rows - 1) / rows;
+  const int rb = blockIdx.x % nrb, rest = blockIdx.x / nrb;
+  const int cb = rest % cols, b = rest / cols;
+  const int x0 = cb * XS;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int m = lane & 15, kg = lane >> 4;
+  // channel 8 h + j of two pixels as one word (the left pixel in the low half)
+  auto put8 = [](uint32_t* dst, int stride_words, const uint4& v0, const uint4& v1) {
+    const uint32_t a[4] = {v0.x, v0.y, v0.z, v0.w}, c[4] = {v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      dst[(2 * k) * stride_words] = (a[k] & 0xffffu) | (c[k] << 16);
+      dst[(2 * k + 1) * stride_words] = (a[k] >> 16) | (c[k] & 0xffff0000u);
+    }
+  };
+  f32x4 acc[9], accb = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int k = 0; k < 9; ++k) acc[k] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const short one = 0x3f80;   // BF16 1.0
+  const bf16x8 ones = {one, one, one, one, one, one, one, one};
+  const int y0 = rb * rows, y1 = min(H, y0 + rows);
+  for (int ys = y0; ys < y1; ys += kWgStage) {
+    const int ny = min(kWgStage, y1 - ys);
+    __syncthreads();   // the previous stage's reads are done
+    // input rows ys - 1 .. ys + 8, column pairs (xx, xx + 1) for xx = -2, 0, .., 64
+    for (int e = tid; e < XR * 34 * 2; e += 256) {
+      const int h = e & 1, q = e >> 1, r = q / 34, xx = 2 * (q - r * 34) - 2;
+      const int gy = ys - 1 + r, gx = x0 + xx;
+      uint4 v0 = make_uint4(0u, 0u, 0u, 0u), v1 = v0;
+      if (gy >= 0 && gy < H) {
+        const uint16_t* src = in16 + (((size_t)b * H + gy) * W + gx) * 16 + 8 * h;
+        if (gx >= 0 && gx < W) v0 = *reinterpret_cast<const uint4*>(src);
+        if (gx + 1 >= 0 && gx + 1 < W) v1 = *reinterpret_cast<const uint4*>(src + 16);
+      }
+      put8(sx + ((r * 16 + 8 * h) * kWgXP + 8 + xx) / 2, kWgXP / 2, v0, v1);
+    }
+    // dz rows ys .. ys + ny - 1, column pairs (xx, xx + 1) for xx = 0, 2, .., 62
+    for (int e = tid; e < kWgStage * 32 * 2; e += 256) {
+      const int h = e & 1, q = e >> 1, r = q >> 5, xx = 2 * (q & 31);
+      uint4 v0 = make_uint4(0u, 0u, 0u, 0u), v1 = v0;
+      if (r < ny) {
+        const uint16_t* src = dz16 + (((size_t)b * H + ys + r) * W + x0 + xx) * 16 + 8 * h;
+        v0 = *reinterpret_cast<const uint4*>(src);
+        v1 = *reinterpret_cast<const uint4*>(src + 16);
+      }
+      put8(sd + ((r * 16 + 8 * h) * kWgDP + xx) / 2, kWgDP / 2, v0, v1);
+    }
+    __syncthreads();
+    for (int rr = wave; rr < ny; rr += 4) {
+#pragma unroll
+      for (int ch = 0; ch < 2; ++ch) {
+        const int p0 = 8 * kg + 32 * ch;   // this lane's 8 pixels: p0 .. p0 + 7
+        const bf16x8 A = *reinterpret_cast<const bf16x8*>(sd + ((rr * 16 + m) * kWgDP + p0) / 2);
+        accb = mfma32(A, ones, accb);
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+          const uint32_t* xr = sx + ((rr + dy) * 16 + m) * (kWgXP / 2) + 4 + p0 / 2;
+          const uint4 V = *reinterpret_cast<const uint4*>(xr);
+          const uint32_t prev = xr[-1], next = xr[4];   // pixels p0 - 2, p0 - 1 and p0 + 8, + 9
+          const uint32_t s01 = __builtin_amdgcn_alignbit(V.y, V.x, 16);
+          const uint32_t s12 = __builtin_amdgcn_alignbit(V.z, V.y, 16);
+          const uint32_t s23 = __builtin_amdgcn_alignbit(V.w, V.z, 16);
+          const uint4 L = make_uint4(__builtin_amdgcn_alignbit(V.x, prev, 16), s01, s12, s23);
+          const uint4 R = make_uint4(s01, s12, s23, __builtin_amdgcn_alignbit(next, V.w, 16));
+          acc[3 * dy + 0] = mfma32(A, __builtin_bit_cast(bf16x8, L), acc[3 * dy + 0]);
+          acc[3 * dy + 1] = mfma32(A, __builtin_bit_cast(bf16x8, V), acc[3 * dy + 1]);
+          acc[3 * dy + 2] = mfma32(A, __builtin_bit_cast(bf16x8, R), acc[3 * dy + 2]);
+        }
+      }
+    }
+  }
+  // lane (m, kg) holds co = 4 kg + i, ci = m of each sum; add the waves' sums in wave order
+  __syncthreads();
+  float4* red = reinterpret_cast<float4*>(sxd);
+#pragma unroll
+  for (int k = 0; k < 9; ++k)
+    red[(wave * 10 + k) * 64 + lane] = make_float4(acc[k][0], acc[k][1], acc[k][2], acc[k][3]);
+  red[(wave * 10 + 9) * 64 + lane] = make_float4(accb[0], accb[1], accb[2], accb[3]);
+  __syncthreads();
+  const float* redf = reinterpret_cast<const float*>(sxd);
+  const int co = tid >> 4, ci = tid & 15, src_lane = 16 * (co >> 2) + ci, i = co & 3;
+  float* dst = partial + (size_t)blockIdx.x * NOUT;
+#pragma unroll
+  for (int k = 0; k < 10; ++k) {
+    if (k == 9 && ci != 0) break;
+    float v = 0.f;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) v += redf[((w * 10 + k) * 64 + src_lane) * 4 + i];
+    if (k < 9) dst[(co * 16 + ci) * 9 + k] = v;
+    else dst[NW + co] = v;
+  }
+}
+
 __global__ void __launch_bounds__(256) cnn_reduce_kernel(const float* __restrict__ partial,
                                                          float* __restrict__ out, int blocks,
                                                          int nout) {
@@ -806,8 +925,8 @@ hipError_t launch_cnn_wgrad(int cin, int cout, const float* dz32, const uint16_t
     hipLaunchKernelGGL((cnn_wgrad_kernel<1, 16>), dim3(blocks), dim3(256), 0, stream, dz32, dz16,
                        in32, in16, partial, H, W, rows);
   else if (cin == 16 && cout == 16)
-    hipLaunchKernelGGL((cnn_wgrad_kernel<16, 16>), dim3(blocks), dim3(256), 0, stream, dz32, dz16,
-                       in32, in16, partial, H, W, rows);
+    hipLaunchKernelGGL(cnn_wgrad16_kernel, dim3(blocks), dim3(256), 0, stream, dz16, in16, partial,
+                       H, W, rows);
   else if (cin == 16 && cout == 1)
     hipLaunchKernelGGL((cnn_wgrad_kernel<16, 1>), dim3(blocks), dim3(256), 0, stream, dz32, dz16,
                        in32, in16, partial, H, W, rows);

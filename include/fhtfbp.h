@@ -265,8 +265,9 @@ int fbp_cnn_forward(const float* img, const uint16_t* w1, const float* b1, const
 
 /* Weight and bias gradients, out[cout * cin * 9 + cout] (FP32): dw[co][ci][tap] =
  * sum_p dz[p][co] in[p + off(tap)][ci], db[co] = sum_p dz[p][co]; dz has cout channels and in
- * cin.  `partial` is caller-owned scratch of fbp_cnn_wgrad_partial_floats floats; the block
- * sums are added in a fixed order (deterministic).  w must be a multiple of 64. */
+ * cin.  `partial` is caller-owned scratch of fbp_cnn_wgrad_partial_floats floats, 8-byte
+ * aligned (FBP_EINVAL otherwise); the block sums are added in a fixed order, in FP64
+ * (deterministic).  w must be a multiple of 64. */
 int64_t fbp_cnn_wgrad_partial_floats(int32_t cin, int32_t cout, int32_t batch, int32_t h,
                                      int32_t w);
 int fbp_cnn_wgrad(int32_t cin, int32_t cout, const float* dz32, const uint16_t* dz16,

@@ -599,20 +599,38 @@ __global__ void __launch_bounds__(256) cnn_wgrad16_kernel(const uint16_t* __rest
   }
 }
 
-__global__ void __launch_bounds__(256) cnn_reduce_kernel(const float* __restrict__ partial,
-                                                         float* __restrict__ out, int blocks,
-                                                         int nout) {
-  __shared__ double sh[256];
-  const int o = blockIdx.x;
+// The blocks' sums added per output in a fixed order, in two steps.  First, block (g, c) takes
+// outputs 64 g .. + 63 and the chunk c of blocks: wave w adds every fourth block of the chunk
+// from its w-th (a wave reads 64 consecutive outputs of a block, 256 bytes), in FP64, and the
+// four waves' sums are added in wave order.  Then each output adds its chunks' sums in chunk
+// order and is rounded to FP32 once.
+__global__ void __launch_bounds__(256) cnn_reduce_blocks_kernel(const float* __restrict__ partial,
+                                                                double* __restrict__ chunk_sums,
+                                                                int blocks, int nout,
+                                                                int per_chunk) {
+  __shared__ double sh[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int o = blockIdx.x * 64 + lane, c = blockIdx.y;
+  const int b0 = c * per_chunk, b1 = min(blocks, b0 + per_chunk);
   double s = 0.0;
-  for (int blk = threadIdx.x; blk < blocks; blk += blockDim.x) s += partial[(size_t)blk * nout + o];
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  for (int d = 128; d > 0; d >>= 1) {
-    if (threadIdx.x < d) sh[threadIdx.x] += sh[threadIdx.x + d];
-    __syncthreads();
+  if (o < nout) {
+#pragma unroll 8
+    for (int blk = b0 + w; blk < b1; blk += 4) s += partial[(size_t)blk * nout + o];
   }
-  if (threadIdx.x == 0) out[o] = (float)sh[0];
+  sh[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && o < nout)
+    chunk_sums[(size_t)c * nout + o] = ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
+}
+
+__global__ void __launch_bounds__(256) cnn_reduce_chunks_kernel(const double* __restrict__ chunk_sums,
+                                                                float* __restrict__ out, int chunks,
+                                                                int nout) {
+  const int o = blockIdx.x * 256 + threadIdx.x;
+  if (o >= nout) return;
+  double s = 0.0;
+  for (int c = 0; c < chunks; ++c) s += chunk_sums[(size_t)c * nout + o];
+  out[o] = (float)s;
 }
 
 // ---- the whole network in one launch (inference) ----------------------------------------------
@@ -915,6 +933,20 @@ hipError_t launch_cnn_conv(int cin, int cout, const float* in32, const uint16_t*
 
 int cnn_wgrad_rows() { return 16; }
 
+namespace {
+constexpr int kReduceChunks = 64;
+// the partial buffer: the blocks' sums (blocks x nout floats), then from the next even float
+// one FP64 sum per chunk of blocks and output
+int64_t wgrad_block_floats(int64_t blocks, int64_t nout) { return (blocks * nout + 1) & ~1ll; }
+}  // namespace
+
+int64_t cnn_wgrad_partial_floats(int cin, int cout, int batch, int H, int W) {
+  const int64_t rows = cnn_wgrad_rows();
+  const int64_t blocks = (int64_t)batch * (W / 64) * ((H + rows - 1) / rows);
+  const int64_t nout = cout * cin * 9 + cout;
+  return wgrad_block_floats(blocks, nout) + 2 * (int64_t)kReduceChunks * nout;
+}
+
 hipError_t launch_cnn_wgrad(int cin, int cout, const float* dz32, const uint16_t* dz16,
                             const float* in32, const uint16_t* in16, float* partial, float* out,
                             int batch, int H, int W, hipStream_t stream) {
@@ -934,8 +966,15 @@ hipError_t launch_cnn_wgrad(int cin, int cout, const float* dz32, const uint16_t
     return hipErrorInvalidValue;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(cnn_reduce_kernel, dim3(nout), dim3(256), 0, stream, partial, out, blocks,
-                     nout);
+  const int per_chunk = (blocks + kReduceChunks - 1) / kReduceChunks;
+  const int chunks = (blocks + per_chunk - 1) / per_chunk;
+  double* chunk_sums = reinterpret_cast<double*>(partial + wgrad_block_floats(blocks, nout));
+  hipLaunchKernelGGL(cnn_reduce_blocks_kernel, dim3((nout + 63) / 64, chunks), dim3(256), 0,
+                     stream, partial, chunk_sums, blocks, nout, per_chunk);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(cnn_reduce_chunks_kernel, dim3((nout + 255) / 256), dim3(256), 0, stream,
+                     chunk_sums, out, chunks, nout);
   return hipGetLastError();
 }
 

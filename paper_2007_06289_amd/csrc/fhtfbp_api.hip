@@ -1125,9 +1125,7 @@ int fbp_cnn_forward(const float* img, const uint16_t* w1, const float* b1, const
 int64_t fbp_cnn_wgrad_partial_floats(int32_t cin, int32_t cout, int32_t batch, int32_t h,
                                      int32_t w) {
   if (!cnn_shape_ok(cin, cout) || batch < 1 || h < 1 || w < 64 || (w % 64) != 0) return FBP_EINVAL;
-  const int64_t rows = cnn_wgrad_rows();
-  const int64_t blocks = (int64_t)batch * (w / 64) * ((h + rows - 1) / rows);
-  return blocks * (cout * cin * 9 + cout);
+  return cnn_wgrad_partial_floats(cin, cout, batch, h, w);
 }
 
 int fbp_cnn_wgrad(int32_t cin, int32_t cout, const float* dz32, const uint16_t* dz16,
@@ -1137,8 +1135,10 @@ int fbp_cnn_wgrad(int32_t cin, int32_t cout, const float* dz32, const uint16_t* 
   if (!partial || !out || (cout == 1 && !dz32) || (cout == 16 && !dz16) || (cin == 1 && !in32) ||
       (cin == 16 && !in16))
     return FBP_EINVAL;
-  // a pixel's BF16 channels are read 16 bytes at a time
-  if ((dz16 && !aligned16(dz16)) || (in16 && !aligned16(in16))) return FBP_EINVAL;
+  // a pixel's BF16 channels are read 16 bytes at a time; the chunk sums in partial are FP64
+  if ((dz16 && !aligned16(dz16)) || (in16 && !aligned16(in16)) ||
+      (reinterpret_cast<uintptr_t>(partial) & 7) != 0)
+    return FBP_EINVAL;
   return launch_cnn_wgrad(cin, cout, dz32, dz16, in32, in16, partial, out, batch, h, w,
                           (hipStream_t)stream) == hipSuccess
              ? FBP_OK

@@ -157,6 +157,8 @@ hipError_t launch_cnn_wgrad(int cin, int cout, const float* dz32, const uint16_t
                             const float* in32, const uint16_t* in16, float* partial, float* out,
                             int batch, int H, int W, hipStream_t stream);
 int cnn_wgrad_rows();
+// floats of the weight gradient's partial buffer (block sums, then FP64 chunk sums)
+int64_t cnn_wgrad_partial_floats(int cin, int cout, int batch, int H, int W);
 hipError_t launch_cnn_fused(const float* in, const uint16_t* w1, const float* b1,
                             const uint16_t* w2, const float* b2, const uint16_t* w3,
                             const float* b3, float* out, int batch, int H, int W,

@@ -152,11 +152,20 @@ def test_schedule_candidates_are_all_compositions():
 def test_cnn_entry_points_reject_unaligned_bf16_buffers(lib):
     """The network's BF16 activations, gradients and packed weights move 8 or 16 bytes at a
     time: a pointer off a 16-byte boundary is refused before any launch (the addresses here
-    are never dereferenced)."""
+    are never dereferenced); so is a weight-gradient partial buffer off an 8-byte boundary."""
     ok, odd = 0x10000, 0x10002
     # weight gradient, 16 -> 16 channels: dz and the input are BF16 NHWC
     assert lib.fbp_cnn_wgrad(16, 16, None, odd, None, ok, ok, ok, 1, 64, 64, None) == -1
     assert lib.fbp_cnn_wgrad(16, 16, None, ok, None, odd, ok, ok, 1, 64, 64, None) == -1
+    # the partial buffer ends in FP64 chunk sums: 8-byte aligned
+    assert lib.fbp_cnn_wgrad(16, 16, None, ok, None, ok, ok + 4, ok, 1, 64, 64, None) == -1
+    assert lib.fbp_cnn_wgrad(16, 1, ok, None, None, ok, ok + 4, ok, 1, 64, 64, None) == -1
+    # its size: the block sums (16 x 64 pixels each), then 64 chunk sums per output in FP64
+    for cin, cout in ((16, 16), (16, 1), (1, 16)):
+        nout = cout * cin * 9 + cout
+        blocks = 2 * (128 // 64) * ((40 + 15) // 16)
+        assert lib.fbp_cnn_wgrad_partial_floats(cin, cout, 2, 40, 128) == \
+            (blocks * nout + 1) // 2 * 2 + 2 * 64 * nout
     # convolution: BF16 input, packed weights, output, mask
     args = dict(in32=None, in16=ok, w=ok, bias=None, mask=None, resid=None, o16=ok, o32=None)
     for k in ("in16", "w", "o16", "mask"):

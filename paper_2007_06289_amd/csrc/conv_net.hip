@@ -322,13 +322,11 @@ __global__ void __launch_bounds__(256) cnn_conv16_tile_kernel(const uint16_t* __
 //   dw[co][ci][tap] = sum_p dz[p][co] in[p + off(tap)][ci],   db[co] = sum_p dz[p][co].
 // dz has COUT channels (FP32 image if 1, BF16 NHWC if 16); in has CIN channels (same rule).
 // Each block covers `rows` image rows x 64 columns of one slice and writes its sums to
-// partial[block][COUT * CIN * 9 + COUT].  With 16 x 16 channel pairs, thread co * CIN + ci
-// holds the nine taps of the pair (co, ci), and the bias of co when ci = 0: along a row, the
-// three input values of each window row slide through registers, so one dz value and three new
-// input values feed nine FMAs, and every sum runs over the row's pixels in order, rows in
-// order.  With 16 pairs, thread pair + 16 s takes the columns s, s + 16, s + 32, s + 48 of
-// each row (in that order, rows in order) and the 16 column sets' sums are added in set order
-// at the end, so all 256 threads work.  The input rows
+// partial[block][COUT * CIN * 9 + COUT].  This kernel serves the single-channel layers (16
+// channel pairs; 16 -> 16 runs on the matrix cores in cnn_wgrad16_kernel): thread pair + 16 s
+// holds the nine taps of the pair (co, ci), and the bias of co when ci = 0, for the columns s,
+// s + 16, s + 32, s + 48 of each row (in that order, rows in order), and the 16 column sets'
+// sums are added in set order at the end, so all 256 threads work.  The input rows
 // y - 1, y, y + 1 sit in a ring of three LDS rows (row yy in slot (yy + 3) % 3), so each row
 // is staged once; a thread stages 8 channels of a pixel from one 16-byte load.
 template <int CIN, int COUT>
@@ -343,7 +341,7 @@ __global__ void __launch_bounds__(256) cnn_wgrad_kernel(const float* __restrict_
   constexpr int XS = 64;
   constexpr int P = COUT * CIN;       // channel pairs
   constexpr int S = 256 / P;          // column sets per pair
-  static_assert(P <= 256 && 256 % P == 0 && XS % S == 0, "whole column sets per pair");
+  static_assert(P == 16 && XS % S == 0, "single-channel layers: whole column sets per pair");
   __shared__ __align__(16) float sdz[XS][COUT];
   __shared__ __align__(16) float sin_[3][XS + 2][CIN];
   const int cols = W / XS;
@@ -412,49 +410,22 @@ __global__ void __launch_bounds__(256) cnn_wgrad_kernel(const float* __restrict_
     stage_in(y + 1);
     stage_dz(y);
     __syncthreads();
-    if constexpr (S > 1) {
-      // column set `set`: columns set, set + S, ...; with 16 pairs a wave's reads of one window
-      // value are 64 consecutive floats
+    // column set `set`: columns set, set + S, ...; with 16 pairs a wave's reads of one window
+    // value are 64 consecutive floats
 #pragma unroll
-      for (int k = 0; k < XS / S; ++k) {
-        const int xx = set + S * k;
-        const float d = sdz[xx][co];
-#pragma unroll
-        for (int dy = 0; dy < 3; ++dy) {
-          const float* r = &sin_[(y + dy + 2) % 3][xx][ci];
-#pragma unroll
-          for (int dx = 0; dx < 3; ++dx) acc[3 * dy + dx] = fmaf(d, r[dx * CIN], acc[3 * dy + dx]);
-        }
-        accb += d;
-      }
-    } else {
-      const float* r[3];
-#pragma unroll
-      for (int dy = 0; dy < 3; ++dy) r[dy] = &sin_[(y + dy + 2) % 3][0][ci];
-      // window row dy at columns xx, xx + 1, xx + 2 (LDS columns of the row, offset by one)
-      float wa[3], wb[3];
+    for (int k = 0; k < XS / S; ++k) {
+      const int xx = set + S * k;
+      const float d = sdz[xx][co];
 #pragma unroll
       for (int dy = 0; dy < 3; ++dy) {
-        wa[dy] = r[dy][0];
-        wb[dy] = r[dy][CIN];
-      }
-#pragma unroll 8
-      for (int xx = 0; xx < XS; ++xx) {
-        const float d = sdz[xx][co];
+        const float* r = &sin_[(y + dy + 2) % 3][xx][ci];
 #pragma unroll
-        for (int dy = 0; dy < 3; ++dy) {
-          const float c = r[dy][(xx + 2) * CIN];
-          acc[3 * dy + 0] = fmaf(d, wa[dy], acc[3 * dy + 0]);
-          acc[3 * dy + 1] = fmaf(d, wb[dy], acc[3 * dy + 1]);
-          acc[3 * dy + 2] = fmaf(d, c, acc[3 * dy + 2]);
-          wa[dy] = wb[dy];
-          wb[dy] = c;
-        }
-        accb += d;
+        for (int dx = 0; dx < 3; ++dx) acc[3 * dy + dx] = fmaf(d, r[dx * CIN], acc[3 * dy + dx]);
       }
+      accb += d;
     }
   }
-  if constexpr (S > 1) {
+  {
     // the column sets' sums, added in set order
     __shared__ float sred[256][10];
 #pragma unroll

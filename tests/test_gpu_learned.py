@@ -119,6 +119,26 @@ def test_cnn_fused_forward_equals_layer_by_layer(gpu_lib):
     assert torch.equal(out, fused)
 
 
+@pytest.mark.parametrize("H,W", [(37, 80), (50, 48), (1, 16)])
+def test_cnn_layers_equal_fused_at_ragged_sizes(gpu_lib, H, W):
+    """The per-layer convolutions where every per-layer kernel has partial tiles (32 x 32 tiles
+    for 1 -> 16, 16 x 32 for 16 -> 16, 32 x 30 for 16 -> 1; widths are multiples of 16, as
+    fbp_cnn_conv requires) against the fused network, itself checked against the oracle at
+    ragged sizes: the same matrix-core operations on the same operands, so equal bit for bit."""
+    api = gpu_lib
+    B = 2
+    g = torch.Generator().manual_seed(H * 1000 + W)
+    x0 = torch.randn(B, H, W, generator=g, dtype=torch.float64).to(torch.float32).cuda()
+    w = _cnn_weights(8)
+    p1, p2, p3 = api.fbp_cnn_pack(w["w1"]), api.fbp_cnn_pack(w["w2"]), api.fbp_cnn_pack(w["w3"])
+    fused = api.fbp_cnn_forward(x0, p1, w["b1"], p2, w["b2"], p3, w["b3"])
+    h1 = api.fbp_cnn_conv(1, 16, x0, p1, bias=w["b1"], relu=True)
+    h2 = api.fbp_cnn_conv(16, 16, h1, p2, bias=w["b2"], relu=True)
+    layers = api.fbp_cnn_conv(16, 1, h2, p3, bias=w["b3"], resid=x0)
+    torch.cuda.synchronize()
+    assert torch.equal(fused, layers)
+
+
 @pytest.mark.parametrize("H,W", [(100, 72), (17, 33), (1, 5)])
 def test_cnn_fused_forward_ragged_sizes_match_oracle(gpu_lib, H, W):
     """Sizes that are not multiples of the 16 x 32 tile (partial tiles, a single row)."""
@@ -157,14 +177,16 @@ def test_cnn_backward_matches_oracle(gpu_lib):
         assert _rel(g_, r_) < 3e-2, n
 
 
+@pytest.mark.parametrize("H", [40, 37])
 @pytest.mark.parametrize("cin,cout", [(16, 16), (16, 1), (1, 16)])
-def test_cnn_weight_gradient_matches_fp64(gpu_lib, cin, cout):
+def test_cnn_weight_gradient_matches_fp64(gpu_lib, cin, cout, H):
     """fbp_cnn_wgrad alone: dz and the layer input hold BF16 values, so every product is exact
     in FP32 and only the FP32 sums differ from the FP64 weight gradient (torch's conv2d weight
-    gradient on the CPU) and bias gradient.  Height 40 leaves a partial block of rows, width
-    128 two column blocks; zero padding at every image edge."""
+    gradient on the CPU) and bias gradient.  Heights 40 and 37 leave a partial block of 8 and 5
+    rows (for 16 -> 16 a whole and a partial stage of 8 rows), width 128 two column blocks;
+    zero padding at every image edge."""
     api = gpu_lib
-    B, H, W = 2, 40, 128
+    B, W = 2, 128
     g = torch.Generator().manual_seed(cin * 17 + cout)
 
     def bf16(*shape):
@@ -213,15 +235,18 @@ def _cnn_backward_bf16_reference(x0, w, R):
     return [dx[:, 0], g1, sums(dz1), g2, sums(dz2), g3, sums(dout)]
 
 
-def test_cnn_backward_matches_bf16_reference(gpu_lib):
+@pytest.mark.parametrize("H", [64, 37])
+def test_cnn_backward_matches_bf16_reference(gpu_lib, H):
     """The network's backward pass against an FP64 reference that rounds to BF16 at the same
     points as the kernels: what is left is FP32 accumulation and the rare BF16 rounding that it
     flips (measured 3e-8 to 1.6e-6 over three seeds), far below the percent-level gap to the
-    unrounded FP64 gradient."""
+    unrounded FP64 gradient.  Height 37 leaves partial tiles and partial weight-gradient
+    blocks."""
     import paper_2007_06289_amd.learned as L
     N, B = 64, 2
-    x0 = I.phantom_image(I.random_ellipses(N, 8, seed=6, batch=B), N, supersample=2).to(torch.float32)
-    R = torch.randn(B, N, N, generator=torch.Generator().manual_seed(9))
+    x0 = (I.phantom_image(I.random_ellipses(N, 8, seed=6, batch=B), N, supersample=2)[:, :H]
+          .contiguous().to(torch.float32))
+    R = torch.randn(B, H, N, generator=torch.Generator().manual_seed(9))
     w = _cnn_weights(4)
     params = [w[k].clone().requires_grad_(True) for k in ("w1", "b1", "w2", "b2", "w3", "b3")]
     xg = x0.cuda().requires_grad_(True)

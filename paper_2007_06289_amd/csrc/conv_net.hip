@@ -72,6 +72,24 @@ __device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
+// A block's copy of ITEMS values into LDS, item e = thread + 256 j: each thread issues all of
+// its loads before its first store, so their memory latencies overlap instead of adding up.
+template <int ITEMS, typename Load, typename Store>
+__device__ __forceinline__ void stage_block(int tid, Load load, Store store) {
+  constexpr int PER = (ITEMS + 255) / 256;
+  decltype(load(0)) v[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int e = tid + 256 * j;
+    if (e < ITEMS) v[j] = load(e);
+  }
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int e = tid + 256 * j;
+    if (e < ITEMS) store(e, v[j]);
+  }
+}
+
 // Packs FP32 weights w[cout][cin][9] into the A operand order of the kernel (the K order in
 // the header), 512 values per step (16x16x32: packed[step][lane][j] = Wg[kk(step, lane, j)]
 // [lane % 16], j < 8; a 16x16x16 step uses the first 256, j < 4).  transpose_flip: pack the
@@ -160,11 +178,15 @@ __global__ void __launch_bounds__(256) cnn_conv1_tile_kernel(const float* __rest
   const int m = lane & 15, kg = lane >> 4;
   const int b = blockIdx.x / tiles_per_img, t = blockIdx.x - b * tiles_per_img;
   const int Y0 = (t / tiles_x) * kC1TH, X0 = (t % tiles_x) * kC1TW;
-  for (int e = tid; e < RR * RC; e += 256) {
-    const int r = e / RC, c = e - r * RC;
-    const int gy = Y0 - 1 + r, gx = X0 - 1 + c;
-    sx[e] = (gy >= 0 && gy < H && gx >= 0 && gx < W) ? in32[((size_t)b * H + gy) * W + gx] : 0.f;
-  }
+  stage_block<RR * RC>(
+      tid,
+      [&](int e) {
+        const int r = e / RC, c = e - r * RC;
+        const int gy = Y0 - 1 + r, gx = X0 - 1 + c;
+        return (gy >= 0 && gy < H && gx >= 0 && gx < W) ? in32[((size_t)b * H + gy) * W + gx]
+                                                         : 0.f;
+      },
+      [&](int e, float v) { sx[e] = v; });
   const bf16x4 wa = reinterpret_cast<const bf16x4*>(wop)[lane];
   float bs[4];
 #pragma unroll
@@ -265,15 +287,20 @@ __global__ void __launch_bounds__(256) cnn_conv16_tile_kernel(const uint16_t* __
   const int b = blockIdx.x / tiles_per_img, t = blockIdx.x - b * tiles_per_img;
   const int Y0 = (t / tiles_x) * kC16TH, X0 = (t % tiles_x) * kC16TW;
   // 16 bytes (8 channels of plane h) of one region pixel per step
-  for (int e = tid; e < 2 * RP; e += 256) {
-    const int q = e >> 1, h = e & 1;
-    const int r = q / RC, c = q - r * RC;
-    const int gy = Y0 - 1 + r, gx = X0 - 1 + c;
-    uint4 v = make_uint4(0u, 0u, 0u, 0u);
-    if (gy >= 0 && gy < H && gx >= 0 && gx < W)
-      v = *reinterpret_cast<const uint4*>(in16 + (((size_t)b * H + gy) * W + gx) * 16 + 8 * h);
-    *reinterpret_cast<uint4*>(sin16 + (h * RP + q) * 8) = v;
-  }
+  stage_block<2 * RP>(
+      tid,
+      [&](int e) {
+        const int q = e >> 1, h = e & 1;
+        const int r = q / RC, c = q - r * RC;
+        const int gy = Y0 - 1 + r, gx = X0 - 1 + c;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (gy >= 0 && gy < H && gx >= 0 && gx < W)
+          v = *reinterpret_cast<const uint4*>(in16 + (((size_t)b * H + gy) * W + gx) * 16 + 8 * h);
+        return v;
+      },
+      [&](int e, const uint4& v) {
+        *reinterpret_cast<uint4*>(sin16 + ((e & 1) * RP + (e >> 1)) * 8) = v;
+      });
   bf16x8 wr[3];
   bf16x4 wd[3];
 #pragma unroll
@@ -321,138 +348,13 @@ __global__ void __launch_bounds__(256) cnn_conv16_tile_kernel(const uint16_t* __
 // out[p][co] = sum_{ci, tap} w[co][ci][tap] in[p + off(tap)][ci]:
 //   dw[co][ci][tap] = sum_p dz[p][co] in[p + off(tap)][ci],   db[co] = sum_p dz[p][co].
 // dz has COUT channels (FP32 image if 1, BF16 NHWC if 16); in has CIN channels (same rule).
-// Each block covers `rows` image rows x 64 columns of one slice and writes its sums to
-// partial[block][COUT * CIN * 9 + COUT].  This kernel serves the single-channel layers (16
-// channel pairs; 16 -> 16 runs on the matrix cores in cnn_wgrad16_kernel): thread pair + 16 s
-// holds the nine taps of the pair (co, ci), and the bias of co when ci = 0, for the columns s,
-// s + 16, s + 32, s + 48 of each row (in that order, rows in order), and the 16 column sets'
-// sums are added in set order at the end, so all 256 threads work.  The input rows
-// y - 1, y, y + 1 sit in a ring of three LDS rows (row yy in slot (yy + 3) % 3), so each row
-// is staged once; a thread stages 8 channels of a pixel from one 16-byte load.
-template <int CIN, int COUT>
-__global__ void __launch_bounds__(256) cnn_wgrad_kernel(const float* __restrict__ dz32,
-                                                        const uint16_t* __restrict__ dz16,
-                                                        const float* __restrict__ in32,
-                                                        const uint16_t* __restrict__ in16,
-                                                        float* __restrict__ partial, int H, int W,
-                                                        int rows) {
-  constexpr int NW = COUT * CIN * 9;
-  constexpr int NOUT = NW + COUT;
-  constexpr int XS = 64;
-  constexpr int P = COUT * CIN;       // channel pairs
-  constexpr int S = 256 / P;          // column sets per pair
-  static_assert(P == 16 && XS % S == 0, "single-channel layers: whole column sets per pair");
-  __shared__ __align__(16) float sdz[XS][COUT];
-  __shared__ __align__(16) float sin_[3][XS + 2][CIN];
-  const int cols = W / XS;
-  const int rb = blockIdx.x % ((H + rows - 1) / rows);
-  const int rest = blockIdx.x / ((H + rows - 1) / rows);
-  const int cb = rest % cols, b = rest / cols;
-  const int x0 = cb * XS;
-  const int tid = threadIdx.x;
-  const int pair = tid % P, set = tid / P;
-  const int co = pair / CIN, ci = pair % CIN;
-
-  // 8 BF16 values of one 16-byte load as FP32, stored as two float4
-  auto store8 = [](float* d, const uint4& v) {
-    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-    float f[8];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      f[2 * k] = __uint_as_float(w[k] << 16);
-      f[2 * k + 1] = __uint_as_float(w[k] & 0xffff0000u);
-    }
-    reinterpret_cast<float4*>(d)[0] = make_float4(f[0], f[1], f[2], f[3]);
-    reinterpret_cast<float4*>(d)[1] = make_float4(f[4], f[5], f[6], f[7]);
-  };
-  // dz of image row y
-  auto stage_dz = [&](int y) {
-    const size_t row = ((size_t)b * H + y) * W + x0;
-    if constexpr (COUT == 16) {
-      if (tid < 2 * XS) {
-        const int xx = tid >> 1, h = tid & 1;
-        store8(&sdz[xx][8 * h], *reinterpret_cast<const uint4*>(dz16 + (row + xx) * 16 + 8 * h));
-      }
-    } else {
-      if (tid < XS) sdz[tid][0] = dz32[row + tid];
-    }
-  };
-  // input row yy (zero outside the image) into its ring slot, columns x0 - 1 .. x0 + 64
-  auto stage_in = [&](int yy) {
-    float* dst = &sin_[(yy + 3) % 3][0][0];
-    const bool row_in = yy >= 0 && yy < H;
-    const size_t row = ((size_t)b * H + (row_in ? yy : 0)) * W;
-    if constexpr (CIN == 16) {
-      if (tid < 2 * (XS + 2)) {
-        const int xx = tid >> 1, h = tid & 1, gx = x0 + xx - 1;
-        uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        if (row_in && gx >= 0 && gx < W)
-          v = *reinterpret_cast<const uint4*>(in16 + (row + gx) * 16 + 8 * h);
-        store8(dst + xx * 16 + 8 * h, v);
-      }
-    } else {
-      if (tid < XS + 2) {
-        const int gx = x0 + tid - 1;
-        dst[tid] = (row_in && gx >= 0 && gx < W) ? in32[row + gx] : 0.f;
-      }
-    }
-  };
-
-  float acc[9], accb = 0.f;
-#pragma unroll
-  for (int k = 0; k < 9; ++k) acc[k] = 0.f;
-  const int y0 = rb * rows, y1 = min(H, y0 + rows);
-  stage_in(y0 - 1);
-  stage_in(y0);
-  for (int y = y0; y < y1; ++y) {
-    // the slot of row y + 1 held row y - 2, which the previous row's sums have finished with
-    __syncthreads();
-    stage_in(y + 1);
-    stage_dz(y);
-    __syncthreads();
-    // column set `set`: columns set, set + S, ...; with 16 pairs a wave's reads of one window
-    // value are 64 consecutive floats
-#pragma unroll
-    for (int k = 0; k < XS / S; ++k) {
-      const int xx = set + S * k;
-      const float d = sdz[xx][co];
-#pragma unroll
-      for (int dy = 0; dy < 3; ++dy) {
-        const float* r = &sin_[(y + dy + 2) % 3][xx][ci];
-#pragma unroll
-        for (int dx = 0; dx < 3; ++dx) acc[3 * dy + dx] = fmaf(d, r[dx * CIN], acc[3 * dy + dx]);
-      }
-      accb += d;
-    }
-  }
-  {
-    // the column sets' sums, added in set order
-    __shared__ float sred[256][10];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) sred[tid][k] = acc[k];
-    sred[tid][9] = accb;
-    __syncthreads();
-    if (tid < P) {
-#pragma unroll
-      for (int k = 0; k < 10; ++k) {
-        float v = sred[tid][k];
-        for (int st = 1; st < S; ++st) v += sred[tid + P * st][k];
-        if (k < 9) acc[k] = v;
-        else accb = v;
-      }
-    }
-  }
-  if (tid < P) {
-    float* dst = partial + (size_t)blockIdx.x * NOUT;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) dst[(co * CIN + ci) * 9 + k] = acc[k];
-    if (ci == 0) dst[NW + co] = accb;
-  }
-}
+// Each block of the weight-gradient kernels below covers 16 image rows x 64 columns of one
+// slice and writes its sums to partial[block][COUT * CIN * 9 + COUT] (index (co CIN + ci) 9 +
+// tap, then the bias gradients); the blocks' sums are then added in a fixed order.
 
 // out[o] = sum over blocks of partial[block][o], fixed order, accumulated in double.
 // Weight and bias gradients of the 16 -> 16 convolution on the matrix cores, for the blocks
-// and partial layout of cnn_wgrad_kernel: dw[co][ci][tap] = sum_p dz[p][co] in[p + off(tap)][ci]
+// and partial layout above: dw[co][ci][tap] = sum_p dz[p][co] in[p + off(tap)][ci]
 // as 16x16x32 BF16 products with A[co][k] = dz at 32 consecutive pixels of a row and B[k][ci] =
 // the input at the same pixels moved by the tap (products of BF16 values are exact, sums are
 // FP32), and db[co] = sum_p dz[p][co] as one more product against B = 1.  A block covers 16 rows
@@ -502,28 +404,43 @@ __global__ void __launch_bounds__(256) cnn_wgrad16_kernel(const uint16_t* __rest
     const int ny = min(kWgStage, y1 - ys);
     __syncthreads();   // the previous stage's reads are done
     // input rows ys - 1 .. ys + 8, column pairs (xx, xx + 1) for xx = -2, 0, .., 64
-    for (int e = tid; e < XR * 34 * 2; e += 256) {
-      const int h = e & 1, q = e >> 1, r = q / 34, xx = 2 * (q - r * 34) - 2;
-      const int gy = ys - 1 + r, gx = x0 + xx;
-      uint4 v0 = make_uint4(0u, 0u, 0u, 0u), v1 = v0;
-      if (gy >= 0 && gy < H) {
-        const uint16_t* src = in16 + (((size_t)b * H + gy) * W + gx) * 16 + 8 * h;
-        if (gx >= 0 && gx < W) v0 = *reinterpret_cast<const uint4*>(src);
-        if (gx + 1 >= 0 && gx + 1 < W) v1 = *reinterpret_cast<const uint4*>(src + 16);
-      }
-      put8(sx + ((r * 16 + 8 * h) * kWgXP + 8 + xx) / 2, kWgXP / 2, v0, v1);
-    }
+    struct Pair {
+      uint4 a, c;
+    };
+    stage_block<XR * 34 * 2>(
+        tid,
+        [&](int e) {
+          const int h = e & 1, q = e >> 1, r = q / 34, xx = 2 * (q - r * 34) - 2;
+          const int gy = ys - 1 + r, gx = x0 + xx;
+          Pair v = {make_uint4(0u, 0u, 0u, 0u), make_uint4(0u, 0u, 0u, 0u)};
+          if (gy >= 0 && gy < H) {
+            const uint16_t* src = in16 + (((size_t)b * H + gy) * W + gx) * 16 + 8 * h;
+            if (gx >= 0 && gx < W) v.a = *reinterpret_cast<const uint4*>(src);
+            if (gx + 1 >= 0 && gx + 1 < W) v.c = *reinterpret_cast<const uint4*>(src + 16);
+          }
+          return v;
+        },
+        [&](int e, const Pair& v) {
+          const int h = e & 1, q = e >> 1, r = q / 34, xx = 2 * (q - r * 34) - 2;
+          put8(sx + ((r * 16 + 8 * h) * kWgXP + 8 + xx) / 2, kWgXP / 2, v.a, v.c);
+        });
     // dz rows ys .. ys + ny - 1, column pairs (xx, xx + 1) for xx = 0, 2, .., 62
-    for (int e = tid; e < kWgStage * 32 * 2; e += 256) {
-      const int h = e & 1, q = e >> 1, r = q >> 5, xx = 2 * (q & 31);
-      uint4 v0 = make_uint4(0u, 0u, 0u, 0u), v1 = v0;
-      if (r < ny) {
-        const uint16_t* src = dz16 + (((size_t)b * H + ys + r) * W + x0 + xx) * 16 + 8 * h;
-        v0 = *reinterpret_cast<const uint4*>(src);
-        v1 = *reinterpret_cast<const uint4*>(src + 16);
-      }
-      put8(sd + ((r * 16 + 8 * h) * kWgDP + xx) / 2, kWgDP / 2, v0, v1);
-    }
+    stage_block<kWgStage * 32 * 2>(
+        tid,
+        [&](int e) {
+          const int h = e & 1, q = e >> 1, r = q >> 5, xx = 2 * (q & 31);
+          Pair v = {make_uint4(0u, 0u, 0u, 0u), make_uint4(0u, 0u, 0u, 0u)};
+          if (r < ny) {
+            const uint16_t* src = dz16 + (((size_t)b * H + ys + r) * W + x0 + xx) * 16 + 8 * h;
+            v.a = *reinterpret_cast<const uint4*>(src);
+            v.c = *reinterpret_cast<const uint4*>(src + 16);
+          }
+          return v;
+        },
+        [&](int e, const Pair& v) {
+          const int h = e & 1, q = e >> 1, r = q >> 5, xx = 2 * (q & 31);
+          put8(sd + ((r * 16 + 8 * h) * kWgDP + xx) / 2, kWgDP / 2, v.a, v.c);
+        });
     __syncthreads();
     for (int rr = wave; rr < ny; rr += 4) {
 #pragma unroll
@@ -570,24 +487,171 @@ __global__ void __launch_bounds__(256) cnn_wgrad16_kernel(const uint16_t* __rest
   }
 }
 
+// Weight and bias gradients of the single-channel layers on the FP32 matrix cores
+// (16x16x4 steps, FP32 operands: the FP32 output gradient and image stay unrounded), for the
+// blocks and partial layout above (16 rows x 64 columns of one slice).  A step
+// takes 4 consecutive pixels of a row as K; lane (m, kg) holds A[m][kg] and B[kg][m].
+//   1 -> 16: A[co][k] = dz[p_k][co], B[k][t] = in[p_k + off(t)] for taps t < 9 and B[k][9] = 1,
+//     so D[co][t] accumulates dw[co][0][t] and D[co][9] the bias gradient.
+//   16 -> 1: with q = p + off(t), dw[0][ci][t] = sum_q dz[q - off(t)] in[q][ci]: A[t][k] =
+//     dz[q_k - off(t)] (dz zero outside the block's pixels), B[k][ci] = in[q_k][ci] over the
+//     block's pixels and their one-pixel border, so D[t][ci] accumulates dw[0][ci][t]; the
+//     centre tap's lanes (A = dz[q]) also add up the bias gradient.
+// The whole block is staged in LDS at once; wave w takes every fourth row from its w-th, and
+// the four waves' sums are added in wave order.
+template <int CIN, int COUT>
+__global__ void __launch_bounds__(256) cnn_wgrad1_kernel(const float* __restrict__ dz32,
+                                                         const uint16_t* __restrict__ dz16,
+                                                         const float* __restrict__ in32,
+                                                         const uint16_t* __restrict__ in16,
+                                                         float* __restrict__ partial, int H,
+                                                         int W) {
+  static_assert((CIN == 1 && COUT == 16) || (CIN == 16 && COUT == 1), "single-channel layers");
+  constexpr int XS = 64, RB = 16, NW = COUT * CIN * 9, NOUT = NW + COUT;
+  constexpr bool kIn1 = CIN == 1;
+  // 1 -> 16: input FP32 [RB + 2][68] (rows y0 - 1 .., columns x0 - 1 ..), dz BF16 [RB][64][16]
+  // 16 -> 1: input BF16 [RB + 2][68][16] (rows y0 - 1 .., columns x0 - 1 ..), dz FP32
+  //          [RB + 4][72] (rows y0 - 2 .., columns x0 - 2 ..)
+  constexpr int XC = 68;
+  constexpr int IN_BYTES = kIn1 ? (RB + 2) * XC * 4 : (RB + 2) * XC * 16 * 2;
+  constexpr int DZ_BYTES = kIn1 ? RB * XS * 16 * 2 : (RB + 4) * 72 * 4;
+  static_assert(IN_BYTES % 16 == 0 && IN_BYTES + DZ_BYTES >= (4 * 64 * 4 + 16) * 4,
+                "aligned areas; the wave sums fit");
+  __shared__ __align__(16) unsigned char smem[IN_BYTES + DZ_BYTES];
+  const int nrb = (H + RB - 1) / RB, cols = W / XS;
+  const int rb = blockIdx.x % nrb, rest = blockIdx.x / nrb;
+  const int cb = rest % cols, b = rest / cols;
+  const int x0 = cb * XS, y0 = rb * RB, ny = min(RB, H - y0);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int m = lane & 15, kg = lane >> 4;
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  float bsum = 0.f;
+  if constexpr (kIn1) {
+    float* sx = reinterpret_cast<float*>(smem);
+    uint16_t* sdz = reinterpret_cast<uint16_t*>(smem + IN_BYTES);
+    stage_block<(RB + 2) * XC>(
+        tid,
+        [&](int e) {
+          const int r = e / XC, c = e - r * XC, gy = y0 - 1 + r, gx = x0 - 1 + c;
+          return (c < XS + 2 && gy >= 0 && gy < H && gx >= 0 && gx < W)
+                     ? in32[((size_t)b * H + gy) * W + gx] : 0.f;
+        },
+        [&](int e, float v) { sx[e] = v; });
+    stage_block<RB * XS * 2>(
+        tid,
+        [&](int e) {
+          const int r = e >> 7, px = (e >> 1) & 63, h = e & 1;
+          uint4 v = make_uint4(0u, 0u, 0u, 0u);
+          if (r < ny)
+            v = *reinterpret_cast<const uint4*>(
+                dz16 + (((size_t)b * H + y0 + r) * W + x0 + px) * 16 + 8 * h);
+          return v;
+        },
+        [&](int e, const uint4& v) {
+          const int r = e >> 7, px = (e >> 1) & 63, h = e & 1;
+          *reinterpret_cast<uint4*>(sdz + (r * XS + px) * 16 + 8 * h) = v;
+        });
+    __syncthreads();
+    const int dy = m / 3, dx = m % 3;
+    for (int rr = wave; rr < ny; rr += 4) {
+#pragma unroll 4
+      for (int g = 0; g < XS / 4; ++g) {
+        const int p = 4 * g + kg;
+        const float a = bf2f(sdz[(rr * XS + p) * 16 + m]);
+        const float bv = m < 9 ? sx[(rr + dy) * XC + p + dx] : (m == 9 ? 1.f : 0.f);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc, 0, 0, 0);
+      }
+    }
+  } else {
+    uint16_t* sx = reinterpret_cast<uint16_t*>(smem);
+    float* sdz = reinterpret_cast<float*>(smem + IN_BYTES);
+    stage_block<(RB + 2) * XC * 2>(
+        tid,
+        [&](int e) {
+          const int q = e >> 1, h = e & 1, r = q / XC, c = q - r * XC;
+          const int gy = y0 - 1 + r, gx = x0 - 1 + c;
+          uint4 v = make_uint4(0u, 0u, 0u, 0u);
+          if (gy >= 0 && gy < H && gx >= 0 && gx < W)
+            v = *reinterpret_cast<const uint4*>(in16 + (((size_t)b * H + gy) * W + gx) * 16 +
+                                                8 * h);
+          return v;
+        },
+        [&](int e, const uint4& v) { *reinterpret_cast<uint4*>(sx + e * 8) = v; });
+    // the block's own pixels only: rows y0 .. y0 + ny - 1, columns x0 .. x0 + 63
+    stage_block<(RB + 4) * 72>(
+        tid,
+        [&](int e) {
+          const int r = e / 72, c = e - r * 72;
+          return (r >= 2 && r < 2 + ny && c >= 2 && c < 2 + XS)
+                     ? dz32[((size_t)b * H + y0 - 2 + r) * W + x0 - 2 + c] : 0.f;
+        },
+        [&](int e, float v) { sdz[e] = v; });
+    __syncthreads();
+    const int dy = m / 3, dx = m % 3;
+    // input rows rr = 0 .. ny + 1 (image rows y0 - 1 ..), 17 groups of 4 columns (x0 - 1 ..)
+    for (int rr = wave; rr < ny + 2; rr += 4) {
+#pragma unroll 4
+      for (int g = 0; g < XC / 4; ++g) {
+        const int qc = 4 * g + kg;
+        const float bv = bf2f(sx[(rr * XC + qc) * 16 + m]);
+        const float a = m < 9 ? sdz[(rr - dy + 2) * 72 + qc - dx + 2] : 0.f;
+        if (m == 4) bsum += a;
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc, 0, 0, 0);
+      }
+    }
+  }
+  // the waves' sums, added in wave order (lane (m, kg) holds D[4 kg + i][m])
+  __syncthreads();
+  float* red = reinterpret_cast<float*>(smem);
+  *reinterpret_cast<float4*>(red + (wave * 64 + lane) * 4) = make_float4(acc[0], acc[1], acc[2],
+                                                                         acc[3]);
+  if (!kIn1 && m == 4) red[4 * 64 * 4 + wave * 4 + kg] = bsum;
+  __syncthreads();
+  if (tid < NOUT) {
+    int row, col;   // of D
+    if constexpr (kIn1) {
+      row = tid < NW ? tid / 9 : tid - NW;   // co
+      col = tid < NW ? tid % 9 : 9;          // tap, or the ones column
+    } else {
+      row = tid % 9;                         // tap
+      col = tid / 9;                         // ci
+    }
+    float v = 0.f;
+    if (kIn1 || tid < NW) {
+      const int src = 16 * (row >> 2) + col, i = row & 3;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) v += red[(w * 64 + src) * 4 + i];
+    } else {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) v += red[4 * 64 * 4 + k];
+    }
+    partial[(size_t)blockIdx.x * NOUT + tid] = v;
+  }
+}
+
 // The blocks' sums added per output in a fixed order, in two steps.  First, block (g, c) takes
-// outputs 64 g .. + 63 and the chunk c of blocks: wave w adds every fourth block of the chunk
-// from its w-th (a wave reads 64 consecutive outputs of a block, 256 bytes), in FP64, and the
-// four waves' sums are added in wave order.  Then each output adds its chunks' sums in chunk
-// order and is rounded to FP32 once.
+// outputs 64 g .. + 63 and the chunk c of kWgChunk blocks: wave w adds blocks w, w + 4, .. of
+// the chunk (a wave reads 64 consecutive outputs of a block, 256 bytes; all its loads issued
+// before the sums), in FP64, and the four waves' sums are added in wave order.  Then each
+// output adds its chunks' sums in chunk order (loaded 32 at a time) and is rounded to FP32 once.
+constexpr int kWgChunk = 32;
 __global__ void __launch_bounds__(256) cnn_reduce_blocks_kernel(const float* __restrict__ partial,
                                                                 double* __restrict__ chunk_sums,
-                                                                int blocks, int nout,
-                                                                int per_chunk) {
+                                                                int blocks, int nout) {
   __shared__ double sh[4][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int o = blockIdx.x * 64 + lane, c = blockIdx.y;
-  const int b0 = c * per_chunk, b1 = min(blocks, b0 + per_chunk);
-  double s = 0.0;
-  if (o < nout) {
-#pragma unroll 8
-    for (int blk = b0 + w; blk < b1; blk += 4) s += partial[(size_t)blk * nout + o];
+  const int b0 = c * kWgChunk;
+  float v[kWgChunk / 4];
+#pragma unroll
+  for (int j = 0; j < kWgChunk / 4; ++j) {
+    const int blk = b0 + w + 4 * j;
+    v[j] = (o < nout && blk < blocks) ? partial[(size_t)blk * nout + o] : 0.f;
   }
+  double s = 0.0;
+#pragma unroll
+  for (int j = 0; j < kWgChunk / 4; ++j) s += (double)v[j];
   sh[w][lane] = s;
   __syncthreads();
   if (w == 0 && o < nout)
@@ -600,7 +664,14 @@ __global__ void __launch_bounds__(256) cnn_reduce_chunks_kernel(const double* __
   const int o = blockIdx.x * 256 + threadIdx.x;
   if (o >= nout) return;
   double s = 0.0;
-  for (int c = 0; c < chunks; ++c) s += chunk_sums[(size_t)c * nout + o];
+  for (int c0 = 0; c0 < chunks; c0 += 32) {
+    double v[32];
+#pragma unroll
+    for (int j = 0; j < 32; ++j)
+      v[j] = c0 + j < chunks ? chunk_sums[(size_t)(c0 + j) * nout + o] : 0.0;
+#pragma unroll
+    for (int j = 0; j < 32; ++j) s += v[j];
+  }
   out[o] = (float)s;
 }
 
@@ -905,9 +976,8 @@ hipError_t launch_cnn_conv(int cin, int cout, const float* in32, const uint16_t*
 int cnn_wgrad_rows() { return 16; }
 
 namespace {
-constexpr int kReduceChunks = 64;
 // the partial buffer: the blocks' sums (blocks x nout floats), then from the next even float
-// one FP64 sum per chunk of blocks and output
+// one FP64 sum per chunk of kWgChunk blocks and output
 int64_t wgrad_block_floats(int64_t blocks, int64_t nout) { return (blocks * nout + 1) & ~1ll; }
 }  // namespace
 
@@ -915,7 +985,8 @@ int64_t cnn_wgrad_partial_floats(int cin, int cout, int batch, int H, int W) {
   const int64_t rows = cnn_wgrad_rows();
   const int64_t blocks = (int64_t)batch * (W / 64) * ((H + rows - 1) / rows);
   const int64_t nout = cout * cin * 9 + cout;
-  return wgrad_block_floats(blocks, nout) + 2 * (int64_t)kReduceChunks * nout;
+  const int64_t chunks = (blocks + kWgChunk - 1) / kWgChunk;
+  return wgrad_block_floats(blocks, nout) + 2 * chunks * nout;
 }
 
 hipError_t launch_cnn_wgrad(int cin, int cout, const float* dz32, const uint16_t* dz16,
@@ -924,24 +995,25 @@ hipError_t launch_cnn_wgrad(int cin, int cout, const float* dz32, const uint16_t
   const int rows = cnn_wgrad_rows();
   const int blocks = batch * (W / 64) * ((H + rows - 1) / rows);
   const int nout = cout * cin * 9 + cout;
+  if (rows != 16) return hipErrorInvalidValue;   // the kernels' row blocks
   if (cin == 1 && cout == 16)
-    hipLaunchKernelGGL((cnn_wgrad_kernel<1, 16>), dim3(blocks), dim3(256), 0, stream, dz32, dz16,
-                       in32, in16, partial, H, W, rows);
+    hipLaunchKernelGGL((cnn_wgrad1_kernel<1, 16>), dim3(blocks), dim3(256), 0, stream, dz32, dz16,
+                       in32, in16, partial, H, W);
   else if (cin == 16 && cout == 16)
     hipLaunchKernelGGL(cnn_wgrad16_kernel, dim3(blocks), dim3(256), 0, stream, dz16, in16, partial,
                        H, W, rows);
   else if (cin == 16 && cout == 1)
-    hipLaunchKernelGGL((cnn_wgrad_kernel<16, 1>), dim3(blocks), dim3(256), 0, stream, dz32, dz16,
-                       in32, in16, partial, H, W, rows);
+    hipLaunchKernelGGL((cnn_wgrad1_kernel<16, 1>), dim3(blocks), dim3(256), 0, stream, dz32, dz16,
+                       in32, in16, partial, H, W);
   else
     return hipErrorInvalidValue;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int per_chunk = (blocks + kReduceChunks - 1) / kReduceChunks;
-  const int chunks = (blocks + per_chunk - 1) / per_chunk;
+  const int chunks = (blocks + kWgChunk - 1) / kWgChunk;
+  if (chunks > 65535) return hipErrorInvalidValue;   // grid y
   double* chunk_sums = reinterpret_cast<double*>(partial + wgrad_block_floats(blocks, nout));
   hipLaunchKernelGGL(cnn_reduce_blocks_kernel, dim3((nout + 63) / 64, chunks), dim3(256), 0,
-                     stream, partial, chunk_sums, blocks, nout, per_chunk);
+                     stream, partial, chunk_sums, blocks, nout);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(cnn_reduce_chunks_kernel, dim3((nout + 255) / 256), dim3(256), 0, stream,

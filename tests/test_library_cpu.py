@@ -160,12 +160,14 @@ def test_cnn_entry_points_reject_unaligned_bf16_buffers(lib):
     # the partial buffer ends in FP64 chunk sums: 8-byte aligned
     assert lib.fbp_cnn_wgrad(16, 16, None, ok, None, ok, ok + 4, ok, 1, 64, 64, None) == -1
     assert lib.fbp_cnn_wgrad(16, 1, ok, None, None, ok, ok + 4, ok, 1, 64, 64, None) == -1
-    # its size: the block sums (16 x 64 pixels each), then 64 chunk sums per output in FP64
+    # its size: the block sums (16 x 64 pixels each), then per output one FP64 sum per chunk
+    # of 32 blocks
     for cin, cout in ((16, 16), (16, 1), (1, 16)):
         nout = cout * cin * 9 + cout
-        blocks = 2 * (128 // 64) * ((40 + 15) // 16)
-        assert lib.fbp_cnn_wgrad_partial_floats(cin, cout, 2, 40, 128) == \
-            (blocks * nout + 1) // 2 * 2 + 2 * 64 * nout
+        for b, h, w in ((2, 40, 128), (8, 1024, 1024)):
+            blocks = b * (w // 64) * ((h + 15) // 16)
+            assert lib.fbp_cnn_wgrad_partial_floats(cin, cout, b, h, w) == \
+                (blocks * nout + 1) // 2 * 2 + 2 * ((blocks + 31) // 32) * nout
     # convolution: BF16 input, packed weights, output, mask
     args = dict(in32=None, in16=ok, w=ok, bias=None, mask=None, resid=None, o16=ok, o32=None)
     for k in ("in16", "w", "o16", "mask"):

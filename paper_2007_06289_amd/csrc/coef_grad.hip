@@ -91,13 +91,42 @@ __global__ void __launch_bounds__(512) coef_grad_kernel(PassArgs A, const float*
   const int row0 = tile * R;
   float* X = S;
   float* Gs = S + R * A.rs;
-  // load x and g rows (natural shift order, skewed)
+  // load x and g rows (natural shift order, skewed): four consecutive samples per load (one
+  // chunk, so four consecutive skewed slots), and each thread issues the loads of 4 rounds
+  // before their stores, so that their memory latencies overlap
   const float* xs = A.in + ((size_t)bq * N + row0) * N;
   const float* gs = gin + ((size_t)bq * N + row0) * N;
-  for (int e = threadIdx.x; e < R * N; e += blockDim.x) {
-    const int r = e >> A.log2n, s = e & mask;
-    X[r * A.rs + skew(s, A.log2l)] = xs[e];
-    Gs[r * A.rs + skew(s, A.log2l)] = gs[e];
+  if (((reinterpret_cast<uintptr_t>(xs) | reinterpret_cast<uintptr_t>(gs)) & 15) == 0) {
+    constexpr int U = 4;
+    const int total4 = (R * N) >> 2;
+    for (int e0 = threadIdx.x; e0 < total4; e0 += U * blockDim.x) {
+      float4 xv[U], gv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * blockDim.x;
+        if (e < total4) {
+          xv[u] = reinterpret_cast<const float4*>(xs)[e];
+          gv[u] = reinterpret_cast<const float4*>(gs)[e];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * blockDim.x;
+        if (e < total4) {
+          const int r = (4 * e) >> A.log2n, s = (4 * e) & mask;
+          float* xd = X + r * A.rs + skew(s, A.log2l);
+          float* gd = Gs + r * A.rs + skew(s, A.log2l);
+          xd[0] = xv[u].x, xd[1] = xv[u].y, xd[2] = xv[u].z, xd[3] = xv[u].w;
+          gd[0] = gv[u].x, gd[1] = gv[u].y, gd[2] = gv[u].z, gd[3] = gv[u].w;
+        }
+      }
+    }
+  } else {
+    for (int e = threadIdx.x; e < R * N; e += blockDim.x) {
+      const int r = e >> A.log2n, s = e & mask;
+      X[r * A.rs + skew(s, A.log2l)] = xs[e];
+      Gs[r * A.rs + skew(s, A.log2l)] = gs[e];
+    }
   }
   __syncthreads();
   const int r = threadIdx.x >> A.log2c, c = threadIdx.x & (C - 1);

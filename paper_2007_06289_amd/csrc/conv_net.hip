@@ -229,6 +229,16 @@ __global__ void __launch_bounds__(256) cnn_conv16to1_tile_kernel(const uint16_t*
   const int m = lane & 15, kg = lane >> 4;
   const int b = blockIdx.x / tiles_per_img, t = blockIdx.x - b * tiles_per_img;
   const int Y0 = (t / tiles_x) * kC3TH, X0 = (t % tiles_x) * kC3TW;
+  // the residual of this thread's output pixels, loaded while the partials are formed
+  constexpr int OUT_PER = (kC3TH * kC3TW + 255) / 256;
+  float rv[OUT_PER];
+#pragma unroll
+  for (int j = 0; j < OUT_PER; ++j) {
+    const int e = tid + 256 * j, r = e / kC3TW, c = e - r * kC3TW;
+    const int gy = Y0 + r, gx = X0 + c;
+    rv[j] = (resid && e < kC3TH * kC3TW && gy < H && gx < W)
+                ? resid[((size_t)b * H + gy) * W + gx] : 0.f;
+  }
   const bf16x4 at = reinterpret_cast<const bf16x4*>(wop)[lane];
   constexpr int PER_WAVE = 2 * PR / 4;
   bf16x4 bv[PER_WAVE];
@@ -251,16 +261,16 @@ __global__ void __launch_bounds__(256) cnn_conv16to1_tile_kernel(const uint16_t*
   }
   __syncthreads();
   const float b0 = bias ? bias[0] : 0.f;
-  for (int e = tid; e < kC3TH * kC3TW; e += 256) {
-    const int r = e / kC3TW, c = e - r * kC3TW;
+#pragma unroll
+  for (int j = 0; j < OUT_PER; ++j) {
+    const int e = tid + 256 * j, r = e / kC3TW, c = e - r * kC3TW;
     const int gy = Y0 + r, gx = X0 + c;
-    if (gy >= H || gx >= W) continue;
+    if (e >= kC3TH * kC3TW || gy >= H || gx >= W) continue;
     const float* q = sp + r * PC + c;
     float sum = q[0];
 #pragma unroll
     for (int tp = 1; tp < 9; ++tp) sum += q[tp * PS + (tp / 3) * PC + tp % 3];
-    const size_t pix = ((size_t)b * H + gy) * W + gx;
-    out32[pix] = sum + b0 + (resid ? resid[pix] : 0.f);
+    out32[((size_t)b * H + gy) * W + gx] = sum + b0 + rv[j];
   }
 }
 

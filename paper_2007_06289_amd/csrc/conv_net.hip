@@ -1,6 +1,7 @@
 // Learned residual correction applied after the reconstruction: 3x3 convolutions (zero
 // padding 1) with 1 or 16 channels, as implicit GEMMs on the matrix cores (BF16 operands, FP32
-// accumulation), plus FP32 weight gradients.
+// accumulation), plus their weight gradients, also on the matrix cores (FP32 sums; BF16
+// operands for 16 -> 16, FP32 operands for the single-channel layers).
 //
 // Activations with 16 channels are stored BF16, NHWC ([b][y][x][c], 32 bytes per pixel);
 // single-channel images are FP32 [b][y][x].  A wave computes 16 consecutive pixels of one row

@@ -248,7 +248,9 @@ int32_t fbp_cnn_packed_elems(int32_t cin);
 
 /* One convolution: cout == 16 writes out16 = relu?(conv + bias) times (mask > 0) when mask is
  * given (the ReLU derivative of the layer below, for the backward pass); cout == 1 writes
- * out32 = conv + bias + resid (resid optional).  bias may be NULL.  w must be a multiple of 16. */
+ * out32 = conv + bias + resid (resid optional, and may be out32 itself).  bias may be NULL.
+ * w must be a multiple of 16.  The output must not overlap the input (the kernels read a halo
+ * of input pixels that other blocks write): FBP_EINVAL before any launch. */
 int fbp_cnn_conv(int32_t cin, int32_t cout, const float* in32, const uint16_t* in16,
                  const uint16_t* wpacked, const float* bias, const uint16_t* mask,
                  const float* resid, uint16_t* out16, float* out32, int32_t relu, int32_t batch,

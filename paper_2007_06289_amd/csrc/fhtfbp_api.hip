@@ -1102,6 +1102,13 @@ int fbp_cnn_conv(int32_t cin, int32_t cout, const float* in32, const uint16_t* i
   if (!aligned16(wpacked) || (in16 && !aligned16(in16)) || (out16 && !aligned16(out16)) ||
       (mask && !aligned16(mask)))
     return FBP_EINVAL;
+  // a block reads input pixels (its halo) that other blocks write: no output over the input
+  const size_t px = (size_t)batch * h * w;
+  const uintptr_t in = cin == 16 ? reinterpret_cast<uintptr_t>(in16) : reinterpret_cast<uintptr_t>(in32);
+  const uintptr_t out =
+      cout == 16 ? reinterpret_cast<uintptr_t>(out16) : reinterpret_cast<uintptr_t>(out32);
+  const size_t in_bytes = px * (cin == 16 ? 32 : 4), out_bytes = px * (cout == 16 ? 32 : 4);
+  if (in < out + out_bytes && out < in + in_bytes) return FBP_EINVAL;
   return launch_cnn_conv(cin, cout, in32, in16, wpacked, bias, mask, resid, out16, out32,
                          relu ? 1 : 0, batch, h, w, (hipStream_t)stream) == hipSuccess
              ? FBP_OK

@@ -174,6 +174,16 @@ def test_cnn_entry_points_reject_unaligned_bf16_buffers(lib):
         a = dict(args, **{k: odd})
         assert lib.fbp_cnn_conv(16, 16, a["in32"], a["in16"], a["w"], a["bias"], a["mask"],
                                 a["resid"], a["o16"], a["o32"], 0, 1, 16, 16, None) == -1
+    # a convolution's output over its input is refused (blocks read a halo that others write)
+    base = 0x100000
+    assert lib.fbp_cnn_conv(16, 16, None, base, ok, None, None, None, base, None, 0, 1, 16, 16,
+                            None) == -1
+    assert lib.fbp_cnn_conv(16, 16, None, base, ok, None, None, None, base + 16 * 16 * 32 - 32,
+                            None, 0, 1, 16, 16, None) == -1
+    assert lib.fbp_cnn_conv(16, 1, None, base, ok, None, None, None, None, base + 64, 0, 1, 16,
+                            16, None) == -1
+    assert lib.fbp_cnn_conv(1, 16, base, None, ok, None, None, None, base - 64, None, 0, 1, 16,
+                            16, None) == -1
     # the fused network: packed weights of each layer
     for i in range(3):
         w = [ok, ok, ok]

@@ -34,7 +34,7 @@ def case(gpu_lib):
     loss.backward()
     torch.cuda.synchronize()
     yield dict(api=api, F=F, plan=plan, lino=lino, phantom=phantom, grad=x.grad.detach().cpu(),
-               loss=float(loss), N=N, B=B)
+               loss=float(loss.detach()), N=N, B=B)
     plan.close()
 
 

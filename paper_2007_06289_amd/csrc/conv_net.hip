@@ -140,14 +140,14 @@ __global__ void cnn_pack_kernel(const float* __restrict__ w, uint16_t* __restric
 // The epilogue of a 16-channel output, shared by the per-layer kernels: lane (m, kg) holds
 // channels 4 kg .. + 3 of pixel pix; bias, then the mask (kept where > 0: the ReLU derivative
 // of the layer below, in the backward pass), BF16, then the optional ReLU, one 8-byte store.
-__device__ __forceinline__ void store_c16(const f32x4& acc, const float (&bs)[4],
-                                          const uint16_t* __restrict__ mask, int relu,
-                                          uint16_t* __restrict__ out16, size_t pix, int kg) {
+// The mask word (the lane's 4 channels of the pixel) is loaded by the caller, ahead of time.
+__device__ __forceinline__ void store_c16(const f32x4& acc, const float (&bs)[4], bool masked,
+                                          uint2 mw, int relu, uint16_t* __restrict__ out16,
+                                          size_t pix, int kg) {
   float v[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) v[j] = acc[j] + bs[j];
-  if (mask) {
-    const uint2 mw = *reinterpret_cast<const uint2*>(mask + pix * 16 + 4 * kg);
+  if (masked) {
     const uint16_t mh[4] = {(uint16_t)mw.x, (uint16_t)(mw.x >> 16), (uint16_t)mw.y,
                             (uint16_t)(mw.y >> 16)};
 #pragma unroll
@@ -179,6 +179,19 @@ __global__ void __launch_bounds__(256) cnn_conv1_tile_kernel(const float* __rest
   const int m = lane & 15, kg = lane >> 4;
   const int b = blockIdx.x / tiles_per_img, t = blockIdx.x - b * tiles_per_img;
   const int Y0 = (t / tiles_x) * kC1TH, X0 = (t % tiles_x) * kC1TW;
+  // the mask words of this lane's output pixels, loaded before the staging
+  uint2 mw[kC1TH / 2];
+  {
+    const int gx = X0 + (wave & 1) * 16 + m, r0 = (wave >> 1) * (kC1TH / 2);
+#pragma unroll
+    for (int i = 0; i < kC1TH / 2; ++i) {
+      const int gy = Y0 + r0 + i;
+      mw[i] = (mask && gx < W && gy < H)
+                  ? *reinterpret_cast<const uint2*>(mask + (((size_t)b * H + gy) * W + gx) * 16 +
+                                                    4 * kg)
+                  : make_uint2(0u, 0u);
+    }
+  }
   stage_block<RR * RC>(
       tid,
       [&](int e) {
@@ -197,7 +210,7 @@ __global__ void __launch_bounds__(256) cnn_conv1_tile_kernel(const float* __rest
   const int gx = X0 + x;
   if (gx >= W) return;   // W is a multiple of 16: whole segments are in or out
   const float* q = sx + (r0 + (kg < 3 ? kg : 0)) * RC + x;
-#pragma unroll 4
+#pragma unroll
   for (int i = 0; i < kC1TH / 2; ++i) {
     const int gy = Y0 + r0 + i;
     if (gy >= H) break;
@@ -205,7 +218,7 @@ __global__ void __launch_bounds__(256) cnn_conv1_tile_kernel(const float* __rest
                                                        pack2_bf16(q[i * RC + 2], 0.f)));
     if (kg == 3) a = bf16x4{0, 0, 0, 0};
     const f32x4 acc = mfma16(wa, a, f32x4{0.f, 0.f, 0.f, 0.f});
-    store_c16(acc, bs, mask, relu, out16, ((size_t)b * H + gy) * W + gx, kg);
+    store_c16(acc, bs, mask != nullptr, mw[i], relu, out16, ((size_t)b * H + gy) * W + gx, kg);
   }
 }
 
@@ -297,6 +310,19 @@ __global__ void __launch_bounds__(256) cnn_conv16_tile_kernel(const uint16_t* __
   const int m = lane & 15, kg = lane >> 4;
   const int b = blockIdx.x / tiles_per_img, t = blockIdx.x - b * tiles_per_img;
   const int Y0 = (t / tiles_x) * kC16TH, X0 = (t % tiles_x) * kC16TW;
+  // the mask words of this lane's output pixels, loaded before the staging
+  uint2 mw[kC16TH / 2];
+  {
+    const int gx = X0 + (wave & 1) * 16 + m, r0 = (wave >> 1) * (kC16TH / 2);
+#pragma unroll
+    for (int i = 0; i < kC16TH / 2; ++i) {
+      const int gy = Y0 + r0 + i;
+      mw[i] = (mask && gx < W && gy < H)
+                  ? *reinterpret_cast<const uint2*>(mask + (((size_t)b * H + gy) * W + gx) * 16 +
+                                                    4 * kg)
+                  : make_uint2(0u, 0u);
+    }
+  }
   // 16 bytes (8 channels of plane h) of one region pixel per step
   stage_block<2 * RP>(
       tid,
@@ -347,7 +373,8 @@ __global__ void __launch_bounds__(256) cnn_conv16_tile_kernel(const uint16_t* __
     acc = mfma16(wd[1], D1, acc);
     acc = mfma16(wd[2], D2, acc);
     const int gy = Y0 + r0 + i;
-    if (gy < H && gx < W) store_c16(acc, bs, mask, relu, out16, ((size_t)b * H + gy) * W + gx, kg);
+    if (gy < H && gx < W)
+      store_c16(acc, bs, mask != nullptr, mw[i], relu, out16, ((size_t)b * H + gy) * W + gx, kg);
     R0 = R1;
     R1 = R2;
     D0 = D1;

@@ -155,6 +155,15 @@ __global__ void __launch_bounds__(512) coef_grad_kernel(PassArgs A, const float*
     const float v = gr[skew(s, A.log2l)];
     return (p >= 0 && p < N) ? ct * v : 0.f;
   };
+  // this lane's input samples (positions base - K .. base + L + K - 1) and output gradient
+  // samples (base .. base + L - 1), read from LDS once; every later use has a fixed offset
+  float xv[L + 2 * K], gv[L];
+#pragma unroll
+  for (int j = 0; j < L + 2 * K; ++j) xv[j] = xin(base - K + j);
+#pragma unroll
+  for (int j = 0; j < L; ++j) gv[j] = gin_(base + j);
+  auto xreg = [&](int p) -> float { return xv[p - base + K]; };
+  auto greg = [&](int p) -> float { return gv[p - base]; };
   float db[K], da[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
@@ -163,13 +172,13 @@ __global__ void __launch_bounds__(512) coef_grad_kernel(PassArgs A, const float*
   }
   {
     float yp[L], ep[K], lam[L], el[K];
-    chunk_rec<L, K, K, +1>(xin, bk, ak, phi, c, C, A.scan_levels, base, yp, ep);
-    chunk_rec<L, K, 1, -1>(gin_, one, ak, phi, c, C, A.scan_levels, base, lam, el);
+    chunk_rec<L, K, K, +1>(xreg, bk, ak, phi, c, C, A.scan_levels, base, yp, ep);
+    chunk_rec<L, K, 1, -1>(greg, one, ak, phi, c, C, A.scan_levels, base, lam, el);
 #pragma unroll
     for (int i = 0; i < L; ++i) {
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        db[k] = fmaf(lam[i], xin(base + i - k), db[k]);
+        db[k] = fmaf(lam[i], xv[i - k + K], db[k]);
         // a[k] is the coefficient of the output delayed by k + 1
         const int d = k + 1;
         const float yv = (i - d >= 0) ? yp[(i - d) >= 0 ? i - d : 0] : ep[(d - i - 1) >= 0 ? d - i - 1 : 0];
@@ -179,13 +188,13 @@ __global__ void __launch_bounds__(512) coef_grad_kernel(PassArgs A, const float*
   }
   {
     float ym[L], em[K], mu[L], eu[K];
-    chunk_rec<L, K, K, -1>(xin, bk, ak, phi, c, C, A.scan_levels, base, ym, em);
-    chunk_rec<L, K, 1, +1>(gin_, one, ak, phi, c, C, A.scan_levels, base, mu, eu);
+    chunk_rec<L, K, K, -1>(xreg, bk, ak, phi, c, C, A.scan_levels, base, ym, em);
+    chunk_rec<L, K, 1, +1>(greg, one, ak, phi, c, C, A.scan_levels, base, mu, eu);
 #pragma unroll
     for (int i = 0; i < L; ++i) {
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        db[k] = fmaf(mu[i], xin(base + i + k), db[k]);
+        db[k] = fmaf(mu[i], xv[i + k + K], db[k]);
         const int d = k + 1;
         const float yv = (i + d < L) ? ym[(i + d) < L ? i + d : 0] : em[(i + d - L) < K ? i + d - L : 0];
         da[k] = fmaf(-mu[i], yv, da[k]);

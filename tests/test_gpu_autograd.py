@@ -80,6 +80,6 @@ def test_backward_is_adjoint_of_forward(case):
     xr = x.clone().requires_grad_(True)
     out = F.fbp_reconstruct_autograd(plan, xr)
     (g,) = torch.autograd.grad(out, xr, grad_outputs=y)
-    lhs = (out.double() * y.double()).sum()
+    lhs = (out.detach().double() * y.double()).sum()
     rhs = (x.double() * g.double()).sum()
     assert abs(float(lhs - rhs)) < 1e-4 * float(lhs.abs() + rhs.abs())
